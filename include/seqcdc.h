@@ -1,0 +1,202 @@
+/*
+ * libseqcdc -- SeqCDC chunk-boundary detection on AMD Instinct MI355X (gfx950).
+ *
+ * SeqCDC (Udayashankar & Al-Kiswany, "Vectorized Sequence-Based Chunking for
+ * Data Deduplication", arXiv 2505.21194) cuts a byte stream into chunks:
+ *   - a chunk ends just after the first run of seq_length bytes that is
+ *     strictly increasing (Increasing mode) or strictly decreasing
+ *     (Decreasing mode)                                       [Sec. III-A]
+ *   - the first min_size - seq_length bytes of every chunk are not scanned,
+ *     so no chunk (except the last) is shorter than min_size  [Sec. III-B]
+ *   - after skip_trigger pairs of bytes in the opposing order, the next
+ *     skip_size bytes are not scanned and the counters restart [Sec. III-C]
+ *   - a chunk ends at max_size bytes if no run is found       [Sec. IV]
+ * Bytes are unsigned; comparisons are strict (an equal pair ends a run and is
+ * not opposing).  A boundary is reported as the exclusive end offset of its
+ * chunk: chunks are [0, cuts[0]), [cuts[0], cuts[1]), ... and the last cut is
+ * the stream length.  An empty stream has no cuts.  At most
+ * floor(n / min_size) + 1 cuts are produced for n bytes.
+ *
+ * Conventions for every call:
+ *   - "d_" pointers are device (HBM) pointers of the current HIP device,
+ *     "h_" pointers are host pointers.  The caller owns every buffer passed
+ *     in; the library never frees them.  Inputs may have any alignment.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   - Return value 0 on success, a negative SEQCDC_E* code on failure.
+ *     seqcdc_last_error() describes the most recent failure of the calling
+ *     thread.  No C++ exception or abort crosses this interface.
+ */
+#ifndef SEQCDC_H
+#define SEQCDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SEQCDC_OK 0
+#define SEQCDC_EINVAL (-1)    /* bad parameters or NULL pointers */
+#define SEQCDC_ECAPACITY (-2) /* output too small; *h_count holds the required count */
+#define SEQCDC_EHIP (-3)      /* a HIP runtime call failed */
+#define SEQCDC_EBUDGET (-4)   /* serving: request larger than the memory budget */
+#define SEQCDC_ENOMEM (-5)    /* host or device allocation failed */
+#define SEQCDC_EAGAIN (-6)    /* serving: result not ready yet */
+#define SEQCDC_ENOENT (-7)    /* serving: unknown ticket */
+
+#define SEQCDC_INCREASING 0u /* Sec. III-A "Modes of operation" */
+#define SEQCDC_DECREASING 1u
+#define SEQCDC_NO_SKIP 0xFFFFFFFFu /* skip_trigger value that disables content-based skipping */
+
+/* SeqCDC parameters (Sec. III; Table I; min/max rule of Sec. VI). */
+typedef struct {
+  uint32_t mode;         /* SEQCDC_INCREASING or SEQCDC_DECREASING */
+  uint32_t seq_length;   /* bytes in the monotone run, 2..16 */
+  uint64_t min_size;     /* >= seq_length */
+  uint64_t max_size;     /* >= min_size */
+  uint32_t skip_trigger; /* opposing pairs that trigger a skip, >= 1; SEQCDC_NO_SKIP disables */
+  uint32_t skip_size;    /* bytes not scanned after the trigger byte */
+} seqcdc_params;
+
+/* Validate a parameter set: 0 or SEQCDC_EINVAL. */
+int seqcdc_params_validate(const seqcdc_params* p);
+
+/* Parameters for a target average chunk size (Increasing mode).  Table I gives
+ * SeqLength 5 with SkipTrigger/SkipSize 55/256, 50/256 and 50/512 for 4, 8 and
+ * 16 KiB; Sec. VI uses min = avg/2 (1 KiB at 4 KiB) and max = 2*avg.  Larger
+ * averages keep 50/512.  avg must be a power of two >= 4096. */
+int seqcdc_params_for_avg(uint64_t avg, seqcdc_params* out);
+
+/* Upper bound on the number of cuts for n bytes: floor(n / min_size) + 1 (0 for n = 0). */
+uint64_t seqcdc_max_cuts(uint64_t n, const seqcdc_params* p);
+
+/* Plans own device workspaces (mark bitmaps: n/4 bytes per n input bytes,
+ * plus per-segment cut lists), pinned staging memory and tuning choices.  A
+ * plan grows on demand.  Calls on one plan must not overlap: the library
+ * waits for the plan's previous call when a call arrives on another stream.
+ * device: HIP device ordinal, or -1 for the current device. */
+typedef struct seqcdc_plan seqcdc_plan;
+int seqcdc_plan_create(int device, seqcdc_plan** out);
+int seqcdc_plan_destroy(seqcdc_plan* plan);
+
+/* Tuning knobs of a plan (0 = keep).  segment_bytes: length of the segments
+ * a stream is split into for speculative resolution (rounded up to 4 KiB);
+ * mark_span_blocks: 1 KiB blocks per mark wave (4, 8 or 16); waves_per_cu:
+ * resident waves per compute unit of the persistent resolve kernels. */
+int seqcdc_plan_set_tuning(seqcdc_plan* plan, uint64_t segment_bytes, uint32_t mark_span_blocks,
+                           uint32_t waves_per_cu);
+/* Current choices for a stream of n bytes under p. */
+int seqcdc_plan_get_tuning(seqcdc_plan* plan, uint64_t n, const seqcdc_params* p, uint64_t* segment_bytes,
+                           uint32_t* mark_span_blocks, uint32_t* waves_per_cu);
+
+/* Autotuner: time candidate segment sizes, mark spans and resolve occupancies
+ * on the given device-resident sample stream, keep the fastest in the plan and
+ * in a process-wide cache keyed by (arch, CU count, seq_length, average class).
+ * Results are exact for every choice; only speed differs.  *best_ms receives
+ * the best time (may be NULL). */
+int seqcdc_autotune(seqcdc_plan* plan, const void* d_sample, uint64_t n, const seqcdc_params* p, double* best_ms,
+                    void* stream);
+
+/* Chunk one device-resident stream (the plain path).
+ * d_stream: n bytes.  d_cuts: room for `cap` uint64 cut offsets.  On return
+ * *h_count is the number of cuts; if it exceeds cap the call returns
+ * SEQCDC_ECAPACITY and only the first cap cuts were written.  Synchronous:
+ * the cuts are in d_cuts when it returns.  plan may be NULL (a per-device
+ * library plan is used). */
+int seqcdc_chunk(const void* d_stream, uint64_t n, const seqcdc_params* p, uint64_t* d_cuts, uint64_t cap,
+                 uint64_t* h_count, void* stream);
+int seqcdc_chunk_plan(seqcdc_plan* plan, const void* d_stream, uint64_t n, const seqcdc_params* p, uint64_t* d_cuts,
+                      uint64_t cap, uint64_t* h_count, void* stream);
+
+/* One file of a batch. */
+typedef struct {
+  const void* d_data;    /* device pointer to the file's bytes */
+  uint64_t n;            /* length in bytes */
+  uint32_t params_index; /* index into the batch's params array */
+  uint32_t reserved;     /* must be 0 */
+} seqcdc_file;
+
+/* Chunk many independent device-resident files in one pass: one mark launch
+ * over all files, a persistent work-stealing resolve over (file, segment)
+ * items (largest first), then stitching and compaction.
+ * h_cut_offsets: host array of nfiles+1 offsets; file f's cuts go to
+ *   d_cuts[h_cut_offsets[f] ..], and each range must hold at least
+ *   seqcdc_max_cuts(n_f, params) entries (checked; SEQCDC_EINVAL otherwise).
+ * d_counts: device array of nfiles uint64 counts (written).
+ * Asynchronous: results are ready once `stream` reaches the end of the call. */
+int seqcdc_chunk_batch(seqcdc_plan* plan, const seqcdc_file* h_files, uint32_t nfiles, const seqcdc_params* h_params,
+                       uint32_t nparams, uint64_t* d_cuts, const uint64_t* h_cut_offsets, uint64_t* d_counts,
+                       void* stream);
+
+/* The mark step alone (Sec. III-D masks), for inspection and tests.
+ * d_eo receives 4 * ceil(n/64) uint32 words: byte q belongs to group q/64;
+ * word 4g+j holds, for the 16 bytes 64g+16j .. 64g+16j+15 (bit i = byte
+ * 64g+16j+i), the run-end bits E in bits 0..15 and the opposing-pair bits O in
+ * bits 16..31.  E marks bytes that end a run of seq_length strictly monotone
+ * bytes; O marks bytes smaller (Increasing) / larger (Decreasing) than their
+ * predecessor.  Asynchronous. */
+int seqcdc_mark(const void* d_stream, uint64_t n, const seqcdc_params* p, uint32_t* d_eo, void* stream);
+
+/* Host convenience: copy h_stream to the device, chunk it, copy the cuts back. */
+int seqcdc_chunk_host(const uint8_t* h_stream, uint64_t n, const seqcdc_params* p, uint64_t* h_cuts, uint64_t cap,
+                      uint64_t* h_count);
+
+/* Space savings of exact-content deduplication (Eq. 1) over the chunks of
+ * several host buffers: chunk i of buffer b is [cuts_b[i-1], cuts_b[i]).
+ * Outputs original bytes, unique bytes, savings = (orig - unique) / orig and
+ * ratio = orig / unique.  Chunks are matched by a 128-bit hash and confirmed
+ * byte for byte. */
+int seqcdc_dedup_stats(const uint8_t* const* h_buffers, const uint64_t* const* h_cut_lists, const uint64_t* h_counts,
+                       uint32_t nbuffers, uint64_t* orig_bytes, uint64_t* unique_bytes, double* savings,
+                       double* ratio);
+
+/* ---------------------------------------------------------------------
+ * Serving: a dedup-ingest request loop with continuous batching.
+ * Requests reference device-resident bytes.  A scheduler thread admits
+ * queued requests while the bytes in flight plus their workspaces fit the
+ * memory budget and a ring slot is free, launches each admitted group as one
+ * batched pass on one of `streams` HIP streams (groups overlap on the GPU),
+ * and publishes each request's cuts and latency when its pass completes.
+ * ------------------------------------------------------------------- */
+typedef struct {
+  int device;                /* -1 = current */
+  uint64_t budget_bytes;     /* device memory for in-flight requests (inputs counted, workspaces included) */
+  uint32_t ring_slots;       /* max requests in flight */
+  uint32_t streams;          /* concurrent batched passes (1..8) */
+  uint32_t max_batch;        /* max requests per pass */
+  uint32_t nparams;          /* parameter sets requests may use */
+  const seqcdc_params* params;
+} seqcdc_server_config;
+
+typedef struct {
+  int32_t status;      /* 0 done, SEQCDC_EAGAIN pending, or an error code */
+  uint32_t reserved;
+  uint64_t count;      /* number of cuts */
+  const uint64_t* cuts; /* host memory owned by the server, valid until seqcdc_server_release(ticket) */
+  double latency_ms;   /* submit -> cuts available on the host */
+  double queue_ms;     /* submit -> admission */
+} seqcdc_result;
+
+typedef struct seqcdc_server seqcdc_server;
+int seqcdc_server_create(const seqcdc_server_config* cfg, seqcdc_server** out);
+/* Queue a request; *ticket identifies it.  SEQCDC_EBUDGET if it could never fit the budget. */
+int seqcdc_server_submit(seqcdc_server* s, const void* d_data, uint64_t n, uint32_t params_index, uint64_t* ticket);
+/* Non-blocking: fills *out; returns 0 when done, SEQCDC_EAGAIN while pending. */
+int seqcdc_server_poll(seqcdc_server* s, uint64_t ticket, seqcdc_result* out);
+/* Block until the ticket is done (timeout_ms < 0: no limit). */
+int seqcdc_server_wait(seqcdc_server* s, uint64_t ticket, double timeout_ms, seqcdc_result* out);
+/* Free the host copy of a finished request's cuts. */
+int seqcdc_server_release(seqcdc_server* s, uint64_t ticket);
+/* Counters: requests admitted, passes launched, peak bytes in flight, peak requests in flight. */
+int seqcdc_server_stats(seqcdc_server* s, uint64_t* admitted, uint64_t* passes, uint64_t* peak_bytes,
+                        uint64_t* peak_inflight);
+int seqcdc_server_destroy(seqcdc_server* s);
+
+/* Description of the calling thread's most recent failure ("" if none). */
+const char* seqcdc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEQCDC_H */

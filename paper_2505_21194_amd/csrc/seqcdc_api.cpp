@@ -1,0 +1,632 @@
+// C ABI of libseqcdc: parameter checks, plans (device workspaces + pinned
+// staging), batch preparation and the launch sequence
+//   mark -> chains -> [continuations -> stitch -> compact]
+// for the plain (one stream) and batched (many files) entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/seqcdc.h"
+#include "seqcdc_internal.h"
+#include "seqcdc_runtime.h"
+
+namespace seqcdc {
+
+hipError_t launch_mark(const FileDesc* d_files, u32 nfiles, u64 total_spans, u32 span_blocks, u32* d_counters,
+                       hipStream_t st);
+hipError_t launch_chains(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32 groups,
+                         hipStream_t st);
+hipError_t launch_continue(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32 groups,
+                           hipStream_t st);
+hipError_t launch_stitch(const FileDesc* d_files, const ChainWs& ws, const u32* d_multi, u32 nmulti,
+                         hipStream_t st);
+hipError_t launch_compact(const FileDesc* d_files, const ChainWs& ws, const u32* d_chains, u32 nchains,
+                          hipStream_t st);
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(SEQCDC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                      \
+  do {                                                     \
+    hipError_t _e = (expr);                                \
+    if (_e != hipSuccess) return hip_fail(_e, #expr);      \
+  } while (0)
+
+int validate(const seqcdc_params* p) {
+  if (!p) return fail(SEQCDC_EINVAL, "params is NULL");
+  if (p->mode > 1) return fail(SEQCDC_EINVAL, "mode must be 0 (increasing) or 1 (decreasing)");
+  if (p->seq_length < 2 || p->seq_length > 16) return fail(SEQCDC_EINVAL, "seq_length must be in [2, 16]");
+  if (p->min_size < p->seq_length) return fail(SEQCDC_EINVAL, "min_size must be >= seq_length");
+  if (p->max_size < p->min_size) return fail(SEQCDC_EINVAL, "max_size must be >= min_size");
+  if (p->skip_trigger < 1) return fail(SEQCDC_EINVAL, "skip_trigger must be >= 1");
+  if (p->max_size > (1ull << 40)) return fail(SEQCDC_EINVAL, "max_size too large");
+  return SEQCDC_OK;
+}
+
+u64 max_cuts(u64 n, const seqcdc_params* p) { return n ? n / p->min_size + 1 : 0; }
+
+static u64 round_up(u64 v, u64 a) { return (v + a - 1) / a * a; }
+
+// ---------------------------------------------------------------- buffers
+int DevBuf::reserve(size_t bytes) {
+  if (bytes <= cap) return SEQCDC_OK;
+  if (p) {
+    (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  size_t want = std::max<size_t>(bytes + bytes / 4, 4096);
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    return fail(SEQCDC_ENOMEM, "hipMalloc(%zu): %s", want, hipGetErrorString(e));
+  }
+  cap = want;
+  return SEQCDC_OK;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  cap = 0;
+}
+
+int HostBuf::reserve(size_t bytes) {
+  if (bytes <= cap) return SEQCDC_OK;
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  cap = 0;
+  size_t want = std::max<size_t>(bytes + bytes / 4, 4096);
+  hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    return fail(SEQCDC_ENOMEM, "hipHostMalloc(%zu): %s", want, hipGetErrorString(e));
+  }
+  cap = want;
+  return SEQCDC_OK;
+}
+
+void HostBuf::release() {
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  cap = 0;
+}
+
+// ---------------------------------------------------------------- tuning
+static std::mutex g_tune_mu;
+static std::vector<TuneEntry> g_tune_cache;
+
+int avg_class(const seqcdc_params* p) {
+  int c = 0;
+  u64 m = p->min_size;
+  while (m > 1) {
+    m >>= 1;
+    c++;
+  }
+  return c;
+}
+
+bool tune_lookup(const TuneKey& k, TuneEntry* out) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  for (auto& e : g_tune_cache)
+    if (e.key == k) {
+      *out = e;
+      return true;
+    }
+  return false;
+}
+
+void tune_store(const TuneEntry& e) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  for (auto& x : g_tune_cache)
+    if (x.key == e.key) {
+      x = e;
+      return;
+    }
+  g_tune_cache.push_back(e);
+}
+
+TuneKey plan_key(const Plan* pl, const seqcdc_params* p) {
+  TuneKey k;
+  k.arch = pl->arch;
+  k.cus = pl->cus;
+  k.sl = p->seq_length;
+  k.avg_class = avg_class(p);
+  return k;
+}
+
+// Segment length for speculative resolution of a stream of n bytes.
+u64 Plan::segment_for(u64 n, const seqcdc_params* p) const {
+  u64 seg = seg_override;
+  if (!seg) {
+    TuneEntry te;
+    if (tune_lookup(plan_key(this, p), &te)) seg = te.seg_mult * p->min_size;
+    else seg = 256 * p->min_size;
+  }
+  seg = std::max<u64>(seg, 64 * 1024);
+  if (n / seg > kMaxSegments) seg = n / kMaxSegments + 1;
+  return round_up(seg, 4096);
+}
+
+u32 Plan::span_blocks_for(const seqcdc_params* p) const {
+  if (span_override) return span_override;
+  TuneEntry te;
+  if (p && tune_lookup(plan_key(this, p), &te)) return te.span_blocks;
+  return 8;
+}
+
+u32 Plan::waves_for(const seqcdc_params* p) const {
+  if (waves_override) return waves_override;
+  TuneEntry te;
+  if (p && tune_lookup(plan_key(this, p), &te)) return te.waves_per_cu;
+  return 8;
+}
+
+// ---------------------------------------------------------------- plans
+int plan_init(Plan* pl, int device) {
+  int dev = device;
+  if (dev < 0) HIP_TRY(hipGetDevice(&dev));
+  pl->device = dev;
+  HIP_TRY(hipSetDevice(dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  pl->cus = (u32)prop.multiProcessorCount;
+  pl->arch = std::string(prop.gcnArchName);
+  HIP_TRY(hipEventCreateWithFlags(&pl->call_done, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&pl->upload_done, hipEventDisableTiming));
+  return SEQCDC_OK;
+}
+
+void plan_free(Plan* pl) {
+  if (pl->pending) (void)hipEventSynchronize(pl->call_done);
+  for (DevBuf* b : {&pl->eo, &pl->list, &pl->cont, &pl->chains, &pl->tables, &pl->misc}) b->release();
+  pl->staging.release();
+  pl->readback.release();
+  if (pl->call_done) (void)hipEventDestroy(pl->call_done);
+  if (pl->upload_done) (void)hipEventDestroy(pl->upload_done);
+}
+
+// A stream of the batch, before device pointers are assigned.
+struct Spec {
+  const uint8_t* data;
+  u64 n;
+  const seqcdc_params* p;
+  u64* out;
+  u64 out_cap;
+  u64* out_count;
+};
+
+template <class T>
+static T* carve(char*& cur, size_t count) {
+  cur = (char*)round_up((u64)cur, 256);
+  T* r = (T*)cur;
+  cur += count * sizeof(T);
+  return r;
+}
+
+static size_t carve_size(std::initializer_list<size_t> parts) {
+  size_t s = 0;
+  for (size_t x : parts) s += round_up(x, 256) + 256;
+  return s;
+}
+
+// Prepare and enqueue the whole pipeline for `specs` on `st`.
+// mark_only: run the mark step only (eo destination = specs[0].out as u32*).
+int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark_only) {
+  if (nfiles == 0) return SEQCDC_OK;
+  HIP_TRY(hipSetDevice(pl->device));
+  // The plan's buffers are reused: a call on another stream must wait for the previous call.
+  if (pl->pending && pl->last_stream != st) HIP_TRY(hipStreamWaitEvent(st, pl->call_done, 0));
+
+  // ---- host-side layout
+  std::vector<FileDesc> fd(nfiles);
+  u64 eo_bytes = 0, spans = 0, list_entries = 0, cont_entries = 0;
+  u32 nchains = 0, cont_cap = 64;
+  const u32 U = pl->span_blocks_for(specs[0].p);
+  const u32 waves = pl->waves_for(specs[0].p);
+  std::vector<u32> multi;
+  for (u32 f = 0; f < nfiles; f++) {
+    const Spec& s = specs[f];
+    FileDesc& d = fd[f];
+    d.data = s.data;
+    d.n = s.n;
+    d.mode = s.p->mode;
+    d.sl = s.p->seq_length;
+    d.min_size = s.p->min_size;
+    d.max_size = s.p->max_size;
+    d.trig = s.p->skip_trigger;
+    d.skip = s.p->skip_size;
+    d.mark_span0 = spans;
+    const u64 blocks = (s.n + kMarkBlock - 1) / kMarkBlock;
+    spans += (blocks + U - 1) / U;
+    d.eo = (u32*)(uintptr_t)eo_bytes;  // offset for now
+    eo_bytes += 16 * ((s.n + 63) / 64);
+    d.seg = pl->segment_for(s.n, s.p);
+    d.nseg = s.n > d.seg ? (u32)((s.n + d.seg - 1) / d.seg) : 1;
+    d.chain0 = nchains;
+    nchains += d.nseg;
+    d.out = s.out;
+    d.out_cap = s.out_cap;
+    d.out_count = s.out_count;
+    if (d.nseg > 1) {
+      multi.push_back(f);
+      cont_cap = std::max<u32>(cont_cap, (u32)std::min<u64>(2 * d.seg / d.min_size + 64, 4096));
+    }
+  }
+  if (mark_only) {
+    fd[0].eo = (u32*)specs[0].out;
+  }
+
+  // chain tables
+  std::vector<u32> chain_file(nchains);
+  std::vector<u64> list_off(nchains, 0), cont_off(nchains, 0);
+  std::vector<u32> order(nchains), border, compact;
+  std::vector<u64> work(nchains);
+  for (u32 f = 0; f < nfiles; f++) {
+    const FileDesc& d = fd[f];
+    for (u32 k = 0; k < d.nseg; k++) {
+      const u32 c = d.chain0 + k;
+      chain_file[c] = f;
+      const u64 S = (u64)k * d.seg;
+      const u64 len = (k + 1 == d.nseg) ? d.n - S : d.seg;
+      work[c] = len;
+      if (d.nseg > 1) {
+        list_off[c] = list_entries;
+        list_entries += len / d.min_size + 2;
+        cont_off[c] = cont_entries;
+        cont_entries += cont_cap;
+        if (k + 1 < d.nseg) border.push_back(c);
+        compact.push_back(c);
+      }
+    }
+  }
+  for (u32 c = 0; c < nchains; c++) order[c] = c;
+  if (nfiles > 1)
+    std::stable_sort(order.begin(), order.end(), [&](u32 a, u32 b) { return work[a] > work[b]; });
+
+  // ---- device workspace
+  int rc;
+  if ((rc = pl->eo.reserve(mark_only ? 256 : eo_bytes + 256))) return rc;
+  if ((rc = pl->list.reserve(std::max<u64>(list_entries, 1) * 8))) return rc;
+  if ((rc = pl->cont.reserve(std::max<u64>(cont_entries, 1) * 8))) return rc;
+  const size_t chain_bytes = carve_size({nchains * 4ull, nchains * 8ull, nchains * 4ull, nchains * 4ull,
+                                         nchains * 4ull, nchains * 4ull, nchains * 4ull, nchains * 4ull,
+                                         nchains * 8ull, nchains * 4ull, nchains * 8ull});
+  if ((rc = pl->chains.reserve(chain_bytes))) return rc;
+  const size_t table_bytes =
+      carve_size({nfiles * sizeof(FileDesc), nchains * 4ull, nchains * 8ull, nchains * 8ull, nchains * 4ull,
+                  border.size() * 4 + 4, multi.size() * 4 + 4, compact.size() * 4 + 4});
+  if ((rc = pl->tables.reserve(table_bytes))) return rc;
+  if ((rc = pl->misc.reserve(4096))) return rc;
+
+  // assign device pointers
+  if (!mark_only)
+    for (u32 f = 0; f < nfiles; f++) fd[f].eo = (u32*)((char*)pl->eo.p + (uintptr_t)fd[f].eo);
+
+  // ---- stage tables (pinned) and upload
+  if (pl->upload_pending) {
+    HIP_TRY(hipEventSynchronize(pl->upload_done));
+    pl->upload_pending = false;
+  }
+  if ((rc = pl->staging.reserve(table_bytes))) return rc;
+  char* h = (char*)pl->staging.p;
+  char* dbase = (char*)pl->tables.p;
+  char* cur = h;
+  FileDesc* h_files = carve<FileDesc>(cur, nfiles);
+  u32* h_chain_file = carve<u32>(cur, nchains);
+  u64* h_list_off = carve<u64>(cur, nchains);
+  u64* h_cont_off = carve<u64>(cur, nchains);
+  u32* h_order = carve<u32>(cur, nchains);
+  u32* h_border = carve<u32>(cur, border.size() + 1);
+  u32* h_multi = carve<u32>(cur, multi.size() + 1);
+  u32* h_compact = carve<u32>(cur, compact.size() + 1);
+  const size_t used = cur - h;
+  memcpy(h_files, fd.data(), nfiles * sizeof(FileDesc));
+  memcpy(h_chain_file, chain_file.data(), nchains * 4ull);
+  memcpy(h_list_off, list_off.data(), nchains * 8ull);
+  memcpy(h_cont_off, cont_off.data(), nchains * 8ull);
+  memcpy(h_order, order.data(), nchains * 4ull);
+  if (!border.empty()) memcpy(h_border, border.data(), border.size() * 4);
+  if (!multi.empty()) memcpy(h_multi, multi.data(), multi.size() * 4);
+  if (!compact.empty()) memcpy(h_compact, compact.data(), compact.size() * 4);
+  auto dev = [&](void* hp) { return (void*)(dbase + ((char*)hp - h)); };
+  HIP_TRY(hipMemcpyAsync(dbase, h, used, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(pl->upload_done, st));
+  pl->upload_pending = true;
+
+  const FileDesc* d_files = (const FileDesc*)dev(h_files);
+  u32* d_counters = (u32*)pl->misc.p;
+
+  // ---- chain workspace
+  ChainWs ws;
+  char* cc = (char*)pl->chains.p;
+  ws.chain_file = (u32*)dev(h_chain_file);
+  ws.list = (u64*)pl->list.p;
+  ws.list_off = (u64*)dev(h_list_off);
+  ws.cont = (u64*)pl->cont.p;
+  ws.cont_off = (u64*)dev(h_cont_off);
+  ws.cont_cap = cont_cap;
+  ws.list_cnt = carve<u32>(cc, nchains);
+  ws.conv_val = carve<u64>(cc, nchains);
+  ws.conv_chain = carve<u32>(cc, nchains);
+  ws.conv_idx = carve<i32>(cc, nchains);
+  ws.cont_cnt = carve<u32>(cc, nchains);
+  ws.active = carve<u32>(cc, nchains);
+  ws.entry_idx = carve<i32>(cc, nchains);
+  ws.jumps = carve<u32>(cc, nchains);
+  ws.out_off = carve<u64>(cc, nchains);
+  ws.covered = (u32*)carve<u64>(cc, nchains);
+  ws.counters = d_counters;
+
+  // ---- launches
+  HIP_TRY(launch_mark(d_files, nfiles, spans, U, d_counters, st));
+  if (!mark_only) {
+    const u32 resident = std::max<u32>(1, pl->cus * waves / kWavesPerGroup);
+    const u32 g_chains = std::min<u32>((nchains + kWavesPerGroup - 1) / kWavesPerGroup, resident);
+    HIP_TRY(launch_chains(d_files, ws, (const u32*)dev(h_order), nchains, g_chains, st));
+    if (!multi.empty()) {
+      const u32 nb = (u32)border.size();
+      const u32 g_b = std::min<u32>((nb + kWavesPerGroup - 1) / kWavesPerGroup, resident);
+      HIP_TRY(launch_continue(d_files, ws, (const u32*)dev(h_border), nb, std::max<u32>(g_b, 1), st));
+      HIP_TRY(launch_stitch(d_files, ws, (const u32*)dev(h_multi), (u32)multi.size(), st));
+      HIP_TRY(launch_compact(d_files, ws, (const u32*)dev(h_compact), (u32)compact.size(), st));
+    }
+  }
+  HIP_TRY(hipEventRecord(pl->call_done, st));
+  pl->pending = true;
+  pl->last_stream = st;
+  pl->last_nchains = nchains;
+  pl->last_multi = (u32)multi.size();
+  return SEQCDC_OK;
+}
+
+static std::mutex g_default_mu;
+static std::vector<Plan*> g_default_plans;
+
+Plan* default_plan(int* rc) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    *rc = hip_fail(e, "hipGetDevice");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> g(g_default_mu);
+  if ((int)g_default_plans.size() <= dev) g_default_plans.resize(dev + 1, nullptr);
+  if (!g_default_plans[dev]) {
+    Plan* pl = new Plan();
+    if ((*rc = plan_init(pl, dev))) {
+      delete pl;
+      return nullptr;
+    }
+    g_default_plans[dev] = pl;
+  }
+  *rc = SEQCDC_OK;
+  return g_default_plans[dev];
+}
+
+int chunk_plan(Plan* pl, const void* d_stream, u64 n, const seqcdc_params* p, u64* d_cuts, u64 cap, u64* h_count,
+               hipStream_t st) {
+  int rc;
+  if ((rc = validate(p))) return rc;
+  if (!h_count) return fail(SEQCDC_EINVAL, "h_count is NULL");
+  if (n == 0) {
+    *h_count = 0;
+    return SEQCDC_OK;
+  }
+  if (!d_stream || (!d_cuts && cap)) return fail(SEQCDC_EINVAL, "NULL stream or cut buffer");
+  std::lock_guard<std::mutex> g(pl->mu);
+  if ((rc = pl->misc.reserve(4096))) return rc;
+  if ((rc = pl->readback.reserve(64))) return rc;
+  Spec s{(const uint8_t*)d_stream, n, p, d_cuts, cap, (u64*)((char*)pl->misc.p + 2048)};
+  if ((rc = run_batch(pl, &s, 1, st, false))) return rc;
+  HIP_TRY(hipMemcpyAsync(pl->readback.p, s.out_count, 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  pl->pending = false;
+  pl->upload_pending = false;
+  *h_count = *(u64*)pl->readback.p;
+  if (*h_count > cap) return fail(SEQCDC_ECAPACITY, "need %llu cuts, capacity %llu", (unsigned long long)*h_count,
+                                  (unsigned long long)cap);
+  return SEQCDC_OK;
+}
+
+int chunk_batch(Plan* pl, const seqcdc_file* files, u32 nfiles, const seqcdc_params* params, u32 nparams,
+                u64* d_cuts, const u64* h_off, u64* d_counts, hipStream_t st) {
+  if (nfiles == 0) return SEQCDC_OK;
+  if (!files || !params || !h_off || !d_counts || !d_cuts) return fail(SEQCDC_EINVAL, "NULL argument");
+  int rc;
+  for (u32 i = 0; i < nparams; i++)
+    if ((rc = validate(&params[i]))) return rc;
+  std::vector<Spec> specs(nfiles);
+  for (u32 f = 0; f < nfiles; f++) {
+    const seqcdc_file& F = files[f];
+    if (F.params_index >= nparams) return fail(SEQCDC_EINVAL, "file %u: params_index out of range", f);
+    if (F.n && !F.d_data) return fail(SEQCDC_EINVAL, "file %u: NULL data", f);
+    if (h_off[f + 1] < h_off[f]) return fail(SEQCDC_EINVAL, "cut offsets must not decrease");
+    const seqcdc_params* p = &params[F.params_index];
+    const u64 room = h_off[f + 1] - h_off[f];
+    if (room < max_cuts(F.n, p))
+      return fail(SEQCDC_EINVAL, "file %u: cut range holds %llu, needs %llu", f, (unsigned long long)room,
+                  (unsigned long long)max_cuts(F.n, p));
+    specs[f] = Spec{(const uint8_t*)F.d_data, F.n, p, d_cuts + h_off[f], room, d_counts + f};
+  }
+  std::lock_guard<std::mutex> g(pl->mu);
+  return run_batch(pl, specs.data(), nfiles, st, false);
+}
+
+}  // namespace seqcdc
+
+using namespace seqcdc;
+
+// ====================================================================== C ABI
+extern "C" {
+
+int seqcdc_params_validate(const seqcdc_params* p) { return validate(p); }
+
+int seqcdc_params_for_avg(uint64_t avg, seqcdc_params* out) {
+  if (!out) return fail(SEQCDC_EINVAL, "out is NULL");
+  if (avg < 4096 || (avg & (avg - 1))) return fail(SEQCDC_EINVAL, "avg must be a power of two >= 4096");
+  out->mode = SEQCDC_INCREASING;
+  out->seq_length = 5;
+  out->skip_trigger = avg == 4096 ? 55 : 50;
+  out->skip_size = avg <= 8192 ? 256 : 512;
+  out->min_size = avg == 4096 ? 1024 : avg / 2;
+  out->max_size = 2 * avg;
+  return SEQCDC_OK;
+}
+
+uint64_t seqcdc_max_cuts(uint64_t n, const seqcdc_params* p) {
+  if (validate(p)) return 0;
+  return max_cuts(n, p);
+}
+
+int seqcdc_plan_create(int device, seqcdc_plan** out) {
+  if (!out) return fail(SEQCDC_EINVAL, "out is NULL");
+  Plan* pl = new (std::nothrow) Plan();
+  if (!pl) return fail(SEQCDC_ENOMEM, "plan allocation failed");
+  int rc = plan_init(pl, device);
+  if (rc) {
+    delete pl;
+    return rc;
+  }
+  *out = (seqcdc_plan*)pl;
+  return SEQCDC_OK;
+}
+
+int seqcdc_plan_destroy(seqcdc_plan* plan) {
+  if (!plan) return SEQCDC_OK;
+  Plan* pl = (Plan*)plan;
+  plan_free(pl);
+  delete pl;
+  return SEQCDC_OK;
+}
+
+int seqcdc_plan_set_tuning(seqcdc_plan* plan, uint64_t segment_bytes, uint32_t mark_span_blocks,
+                           uint32_t waves_per_cu) {
+  if (!plan) return fail(SEQCDC_EINVAL, "plan is NULL");
+  Plan* pl = (Plan*)plan;
+  if (mark_span_blocks && mark_span_blocks != 4 && mark_span_blocks != 8 && mark_span_blocks != 16)
+    return fail(SEQCDC_EINVAL, "mark_span_blocks must be 4, 8 or 16");
+  if (waves_per_cu > 32) return fail(SEQCDC_EINVAL, "waves_per_cu must be <= 32");
+  std::lock_guard<std::mutex> g(pl->mu);
+  if (segment_bytes) pl->seg_override = segment_bytes;
+  if (mark_span_blocks) pl->span_override = mark_span_blocks;
+  if (waves_per_cu) pl->waves_override = waves_per_cu;
+  return SEQCDC_OK;
+}
+
+int seqcdc_plan_get_tuning(seqcdc_plan* plan, uint64_t n, const seqcdc_params* p, uint64_t* segment_bytes,
+                           uint32_t* mark_span_blocks, uint32_t* waves_per_cu) {
+  if (!plan) return fail(SEQCDC_EINVAL, "plan is NULL");
+  int rc = validate(p);
+  if (rc) return rc;
+  Plan* pl = (Plan*)plan;
+  if (segment_bytes) *segment_bytes = pl->segment_for(n, p);
+  if (mark_span_blocks) *mark_span_blocks = pl->span_blocks_for(p);
+  if (waves_per_cu) *waves_per_cu = pl->waves_for(p);
+  return SEQCDC_OK;
+}
+
+int seqcdc_chunk(const void* d_stream, uint64_t n, const seqcdc_params* p, uint64_t* d_cuts, uint64_t cap,
+                 uint64_t* h_count, void* stream) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!h_count) return fail(SEQCDC_EINVAL, "h_count is NULL");
+  if (n == 0) {
+    *h_count = 0;
+    return SEQCDC_OK;
+  }
+  if (!d_stream || (!d_cuts && cap)) return fail(SEQCDC_EINVAL, "NULL stream or cut buffer");
+  Plan* pl = default_plan(&rc);
+  if (!pl) return rc;
+  return chunk_plan(pl, d_stream, n, p, d_cuts, cap, h_count, (hipStream_t)stream);
+}
+
+int seqcdc_chunk_plan(seqcdc_plan* plan, const void* d_stream, uint64_t n, const seqcdc_params* p, uint64_t* d_cuts,
+                      uint64_t cap, uint64_t* h_count, void* stream) {
+  if (!plan) return seqcdc_chunk(d_stream, n, p, d_cuts, cap, h_count, stream);
+  return chunk_plan((Plan*)plan, d_stream, n, p, d_cuts, cap, h_count, (hipStream_t)stream);
+}
+
+int seqcdc_chunk_batch(seqcdc_plan* plan, const seqcdc_file* h_files, uint32_t nfiles, const seqcdc_params* h_params,
+                       uint32_t nparams, uint64_t* d_cuts, const uint64_t* h_cut_offsets, uint64_t* d_counts,
+                       void* stream) {
+  int rc;
+  Plan* pl = plan ? (Plan*)plan : default_plan(&rc);
+  if (!pl) return rc;
+  for (uint32_t f = 0; f < nfiles; f++)
+    if (h_files && h_files[f].reserved) return fail(SEQCDC_EINVAL, "seqcdc_file.reserved must be 0");
+  return chunk_batch(pl, h_files, nfiles, h_params, nparams, d_cuts, h_cut_offsets, d_counts, (hipStream_t)stream);
+}
+
+int seqcdc_mark(const void* d_stream, uint64_t n, const seqcdc_params* p, uint32_t* d_eo, void* stream) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (n == 0) return SEQCDC_OK;
+  if (!d_stream || !d_eo) return fail(SEQCDC_EINVAL, "NULL pointer");
+  Plan* pl = default_plan(&rc);
+  if (!pl) return rc;
+  std::lock_guard<std::mutex> g(pl->mu);
+  if ((rc = pl->misc.reserve(4096))) return rc;
+  Spec s{(const uint8_t*)d_stream, n, p, (u64*)d_eo, 0, nullptr};
+  return run_batch(pl, &s, 1, (hipStream_t)stream, true);
+}
+
+int seqcdc_chunk_host(const uint8_t* h_stream, uint64_t n, const seqcdc_params* p, uint64_t* h_cuts, uint64_t cap,
+                      uint64_t* h_count) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!h_count) return fail(SEQCDC_EINVAL, "h_count is NULL");
+  if (n == 0) {
+    *h_count = 0;
+    return SEQCDC_OK;
+  }
+  if (!h_stream || (!h_cuts && cap)) return fail(SEQCDC_EINVAL, "NULL pointer");
+  void* d_in = nullptr;
+  u64* d_out = nullptr;
+  const u64 need = max_cuts(n, p);
+  HIP_TRY(hipMalloc(&d_in, n));
+  hipError_t e = hipMalloc((void**)&d_out, need * 8);
+  if (e != hipSuccess) {
+    (void)hipFree(d_in);
+    return hip_fail(e, "hipMalloc");
+  }
+  e = hipMemcpy(d_in, h_stream, n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    rc = seqcdc_chunk(d_in, n, p, d_out, need, h_count, nullptr);
+    if (rc == SEQCDC_OK) {
+      const u64 copy = std::min<u64>(*h_count, cap);
+      if (copy) e = hipMemcpy(h_cuts, d_out, copy * 8, hipMemcpyDeviceToHost);
+      if (e == hipSuccess && *h_count > cap) rc = fail(SEQCDC_ECAPACITY, "need %llu cuts", (unsigned long long)*h_count);
+    }
+  }
+  (void)hipFree(d_in);
+  (void)hipFree(d_out);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  return rc;
+}
+
+const char* seqcdc_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

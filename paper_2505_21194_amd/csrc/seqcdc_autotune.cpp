@@ -1,0 +1,103 @@
+// Autotuner: picks the segment length of speculative resolution, the mark
+// span and the resident waves of the persistent resolve kernels by timing
+// candidates on a device-resident sample.  Every candidate produces the same
+// cuts; only speed differs.  Results go to a process-wide cache keyed by
+// (arch, CU count, SeqLength, average class).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/seqcdc.h"
+#include "seqcdc_runtime.h"
+
+namespace seqcdc {
+
+static int time_config(Plan* pl, const void* d, u64 n, const seqcdc_params* p, u64* d_cuts, u64 cap,
+                       hipStream_t st, hipEvent_t e0, hipEvent_t e1, int reps, double* ms) {
+  u64 cnt = 0;
+  int rc = chunk_plan(pl, d, n, p, d_cuts, cap, &cnt, st);  // warm-up (and workspace growth)
+  if (rc) return rc;
+  double best = 1e30;
+  for (int r = 0; r < reps; r++) {
+    hipError_t e = hipEventRecord(e0, st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    rc = chunk_plan(pl, d, n, p, d_cuts, cap, &cnt, st);
+    if (rc) return rc;
+    e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e != hipSuccess) return hip_fail(e, "hipEvent timing");
+    best = std::min(best, (double)t);
+  }
+  *ms = best;
+  return SEQCDC_OK;
+}
+
+}  // namespace seqcdc
+
+using namespace seqcdc;
+
+extern "C" int seqcdc_autotune(seqcdc_plan* plan, const void* d_sample, uint64_t n, const seqcdc_params* p,
+                               double* best_ms, void* stream) {
+  if (!plan) return fail(SEQCDC_EINVAL, "plan is NULL");
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!d_sample || n == 0) return fail(SEQCDC_EINVAL, "empty sample");
+  Plan* pl = (Plan*)plan;
+  hipStream_t st = (hipStream_t)stream;
+  const u64 cap = max_cuts(n, p);
+  u64* d_cuts = nullptr;
+  hipError_t e = hipMalloc((void**)&d_cuts, cap * 8);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+
+  const u64 saved_seg = pl->seg_override;
+  const u32 saved_span = pl->span_override, saved_waves = pl->waves_override;
+  TuneEntry best;
+  best.key = plan_key(pl, p);
+  best.ms = 1e30;
+  auto trial = [&](u64 seg_mult, u32 span, u32 waves) -> int {
+    pl->seg_override = seg_mult * p->min_size;
+    pl->span_override = span;
+    pl->waves_override = waves;
+    double ms = 0;
+    int r = time_config(pl, d_sample, n, p, d_cuts, cap, st, e0, e1, 3, &ms);
+    if (r) return r;
+    if (ms < best.ms) {
+      best.ms = ms;
+      best.seg_mult = seg_mult;
+      best.span_blocks = span;
+      best.waves_per_cu = waves;
+    }
+    return SEQCDC_OK;
+  };
+  // coordinate search: segment length, then mark span, then resolve occupancy
+  for (u64 m : {32ull, 64ull, 128ull, 256ull, 512ull, 1024ull})
+    if ((rc = trial(m, 8, 8))) break;
+  if (!rc) {
+    const u64 m = best.seg_mult;
+    for (u32 s : {4u, 16u})
+      if ((rc = trial(m, s, 8))) break;
+  }
+  if (!rc) {
+    const u64 m = best.seg_mult;
+    const u32 s = best.span_blocks;
+    for (u32 w : {2u, 4u, 16u})
+      if ((rc = trial(m, s, w))) break;
+  }
+  pl->seg_override = saved_seg;
+  pl->span_override = saved_span;
+  pl->waves_override = saved_waves;
+  if (!rc) {
+    tune_store(best);
+    if (best_ms) *best_ms = best.ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(d_cuts);
+  return rc;
+}

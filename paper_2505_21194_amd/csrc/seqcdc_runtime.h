@@ -1,0 +1,79 @@
+// Host runtime internals of libseqcdc: plans, buffers, tuning cache.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+
+#include "../../include/seqcdc.h"
+#include "seqcdc_internal.h"
+
+namespace seqcdc {
+
+constexpr u64 kMaxSegments = 65536;  // per stream
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  int reserve(size_t bytes);
+  void release();
+};
+
+struct HostBuf {  // pinned
+  void* p = nullptr;
+  size_t cap = 0;
+  int reserve(size_t bytes);
+  void release();
+};
+
+struct TuneKey {
+  std::string arch;
+  u32 cus = 0, sl = 0;
+  int avg_class = 0;
+  bool operator==(const TuneKey& o) const {
+    return arch == o.arch && cus == o.cus && sl == o.sl && avg_class == o.avg_class;
+  }
+};
+
+struct TuneEntry {
+  TuneKey key;
+  u64 seg_mult = 256;  // segment length = seg_mult * min_size
+  u32 span_blocks = 8;
+  u32 waves_per_cu = 8;
+  double ms = 0;
+};
+
+struct Plan {
+  int device = 0;
+  u32 cus = 256;
+  std::string arch;
+  std::mutex mu;
+  DevBuf eo, list, cont, chains, tables, misc;
+  HostBuf staging, readback;
+  hipEvent_t call_done = nullptr, upload_done = nullptr;
+  bool pending = false, upload_pending = false;
+  hipStream_t last_stream = nullptr;
+  u32 last_nchains = 0, last_multi = 0;
+  u64 seg_override = 0;
+  u32 span_override = 0, waves_override = 0;
+
+  u64 segment_for(u64 n, const seqcdc_params* p) const;
+  u32 span_blocks_for(const seqcdc_params* p) const;
+  u32 waves_for(const seqcdc_params* p) const;
+};
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+int validate(const seqcdc_params* p);
+u64 max_cuts(u64 n, const seqcdc_params* p);
+int plan_init(Plan* pl, int device);
+void plan_free(Plan* pl);
+int chunk_plan(Plan* pl, const void* d_stream, u64 n, const seqcdc_params* p, u64* d_cuts, u64 cap, u64* h_count,
+               hipStream_t st);
+int chunk_batch(Plan* pl, const seqcdc_file* files, u32 nfiles, const seqcdc_params* params, u32 nparams,
+                u64* d_cuts, const u64* h_off, u64* d_counts, hipStream_t st);
+TuneKey plan_key(const Plan* pl, const seqcdc_params* p);
+bool tune_lookup(const TuneKey& k, TuneEntry* out);
+void tune_store(const TuneEntry& e);
+
+}  // namespace seqcdc
