@@ -53,7 +53,7 @@ typedef struct {
   uint32_t mode;         /* SEQCDC_INCREASING or SEQCDC_DECREASING */
   uint32_t seq_length;   /* bytes in the monotone run, 2..16 */
   uint64_t min_size;     /* >= seq_length */
-  uint64_t max_size;     /* >= min_size */
+  uint64_t max_size;     /* >= min_size, <= 1 GiB */
   uint32_t skip_trigger; /* opposing pairs that trigger a skip, >= 1; SEQCDC_NO_SKIP disables */
   uint32_t skip_size;    /* bytes not scanned after the trigger byte */
 } seqcdc_params;

@@ -59,7 +59,7 @@ int validate(const seqcdc_params* p) {
   if (p->min_size < p->seq_length) return fail(SEQCDC_EINVAL, "min_size must be >= seq_length");
   if (p->max_size < p->min_size) return fail(SEQCDC_EINVAL, "max_size must be >= min_size");
   if (p->skip_trigger < 1) return fail(SEQCDC_EINVAL, "skip_trigger must be >= 1");
-  if (p->max_size > (1ull << 40)) return fail(SEQCDC_EINVAL, "max_size too large");
+  if (p->max_size > (1ull << 30)) return fail(SEQCDC_EINVAL, "max_size must be <= 1 GiB");
   return SEQCDC_OK;
 }
 
@@ -201,7 +201,7 @@ int plan_init(Plan* pl, int device) {
 
 void plan_free(Plan* pl) {
   if (pl->pending) (void)hipEventSynchronize(pl->call_done);
-  for (DevBuf* b : {&pl->eo, &pl->list, &pl->cont, &pl->chains, &pl->tables, &pl->misc}) b->release();
+  for (DevBuf* b : {&pl->eo, &pl->esum, &pl->list, &pl->cont, &pl->chains, &pl->tables, &pl->misc}) b->release();
   pl->staging.release();
   pl->readback.release();
   if (pl->call_done) (void)hipEventDestroy(pl->call_done);
@@ -242,7 +242,7 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
 
   // ---- host-side layout
   std::vector<FileDesc> fd(nfiles);
-  u64 eo_bytes = 0, spans = 0, list_entries = 0, cont_entries = 0;
+  u64 eo_bytes = 0, esum_bytes = 0, spans = 0, list_entries = 0, cont_entries = 0;
   u32 nchains = 0, cont_cap = 64;
   const u32 U = pl->span_blocks_for(specs[0].p);
   const u32 waves = pl->waves_for(specs[0].p);
@@ -261,8 +261,10 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
     d.mark_span0 = spans;
     const u64 blocks = (s.n + kMarkBlock - 1) / kMarkBlock;
     spans += (blocks + U - 1) / U;
-    d.eo = (u32*)(uintptr_t)eo_bytes;  // offset for now
+    d.eo = (u32*)(uintptr_t)eo_bytes;  // offsets for now
     eo_bytes += 16 * ((s.n + 63) / 64);
+    d.esum = (uint8_t*)(uintptr_t)esum_bytes;
+    esum_bytes += round_up((s.n + 1023) / 1024, 16) + 16;
     d.seg = pl->segment_for(s.n, s.p);
     d.nseg = s.n > d.seg ? (u32)((s.n + d.seg - 1) / d.seg) : 1;
     d.chain0 = nchains;
@@ -309,6 +311,7 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   // ---- device workspace
   int rc;
   if ((rc = pl->eo.reserve(mark_only ? 256 : eo_bytes + 256))) return rc;
+  if ((rc = pl->esum.reserve(esum_bytes + 256))) return rc;
   if ((rc = pl->list.reserve(std::max<u64>(list_entries, 1) * 8))) return rc;
   if ((rc = pl->cont.reserve(std::max<u64>(cont_entries, 1) * 8))) return rc;
   const size_t chain_bytes = carve_size({nchains * 4ull, nchains * 8ull, nchains * 4ull, nchains * 4ull,
@@ -322,8 +325,10 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   if ((rc = pl->misc.reserve(4096))) return rc;
 
   // assign device pointers
-  if (!mark_only)
-    for (u32 f = 0; f < nfiles; f++) fd[f].eo = (u32*)((char*)pl->eo.p + (uintptr_t)fd[f].eo);
+  for (u32 f = 0; f < nfiles; f++) {
+    if (!mark_only) fd[f].eo = (u32*)((char*)pl->eo.p + (uintptr_t)fd[f].eo);
+    fd[f].esum = (uint8_t*)pl->esum.p + (uintptr_t)fd[f].esum;
+  }
 
   // ---- stage tables (pinned) and upload
   if (pl->upload_pending) {
@@ -383,12 +388,13 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   // ---- launches
   HIP_TRY(launch_mark(d_files, nfiles, spans, U, d_counters, st));
   if (!mark_only) {
-    const u32 resident = std::max<u32>(1, pl->cus * waves / kWavesPerGroup);
-    const u32 g_chains = std::min<u32>((nchains + kWavesPerGroup - 1) / kWavesPerGroup, resident);
+    // one chain per two-wave workgroup; at most 4 ring workgroups fit a CU's LDS
+    const u32 resident = std::max<u32>(1, pl->cus * std::min<u32>(4, std::max<u32>(1, waves / 2)));
+    const u32 g_chains = std::min<u32>(nchains, resident);
     HIP_TRY(launch_chains(d_files, ws, (const u32*)dev(h_order), nchains, g_chains, st));
     if (!multi.empty()) {
       const u32 nb = (u32)border.size();
-      const u32 g_b = std::min<u32>((nb + kWavesPerGroup - 1) / kWavesPerGroup, resident);
+      const u32 g_b = std::min<u32>(nb, resident);
       HIP_TRY(launch_continue(d_files, ws, (const u32*)dev(h_border), nb, std::max<u32>(g_b, 1), st));
       HIP_TRY(launch_stitch(d_files, ws, (const u32*)dev(h_multi), (u32)multi.size(), st));
       HIP_TRY(launch_compact(d_files, ws, (const u32*)dev(h_compact), (u32)compact.size(), st));

@@ -1,0 +1,43 @@
+// Wave-level device helpers shared by the mark and resolve kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "seqcdc_internal.h"
+
+namespace seqcdc {
+
+typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ u32 lane_id() { return __lane_id(); }
+
+// lane l receives v of lane l-1; lane 0 receives `carry` (DPP wave_shr:1).
+__device__ __forceinline__ u32 shift_up_lanes(u32 v, u32 carry) {
+  return __builtin_amdgcn_update_dpp(carry, v, 0x138, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ u32 readlane(u32 v, u32 l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ u64 readlane64(u64 v, u32 l) {
+  return (u64)readlane((u32)v, l) | ((u64)readlane((u32)(v >> 32), l) << 32);
+}
+__device__ __forceinline__ u64 ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ u32 ctz64(u64 v) { return (u32)__builtin_ctzll(v); }
+
+// Inclusive prefix sum across the wave (DPP row shifts + row broadcasts).
+__device__ __forceinline__ u32 wave_incl_scan(u32 v) {
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, true);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, true);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, true);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, true);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false); // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false); // row_bcast:31
+  return v;
+}
+
+__device__ __forceinline__ u32 wave_pop(u32* head) {
+  u32 v = 0;
+  if (lane_id() == 0) v = atomicAdd(head, 1u);
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+}  // namespace seqcdc

@@ -1,0 +1,725 @@
+// SeqCDC resolve step on CDNA4 (gfx950): the exact sequential state machine
+// of the paper run over the mark bits.
+//
+// From a cut at c (Sec. III-B) scanning starts at s = c + min - SeqLength;
+// the chunk ends one byte past the first run end E at or after s+SeqLength-1
+// (Sec. III-A), unless the SkipTrigger-th opposing pair O after s comes first,
+// in which case SkipSize bytes after it are not scanned and scanning restarts
+// with fresh counters (Sec. III-C); nothing is scanned at or past
+// min(c + max, n) (Sec. IV).  Only the first event in byte order matters: a
+// pair cannot be favourable and opposing at once.
+//
+// Parallelism: a stream is split into segments.  A chain starts at every
+// segment start as if a cut were there (pass A).  The state after a cut
+// depends only on the cut's position, so once two chains share a cut they
+// agree from then on.  Pass B continues each chain past its segment until
+// one of its cuts belongs to the chain that owns that position; the stitch
+// then keeps the exact pieces and the compaction writes them out.
+//
+// Each chain is one workgroup of two waves: a consumer wave runs the state
+// machine and a producer wave streams the mark bits of the next sub-windows
+// (4 KiB of input, 1 KiB of bits each) from HBM into an LDS ring ahead of it,
+// so the consumer never waits on HBM latency in steady state.  A per-1 KiB
+// summary of run ends lets a chain cross regions with no run end (zero runs,
+// most short periodic patterns) without reading their bits: with no run end
+// before the limit, the chunk ends at the limit whatever the opposing pairs do.
+
+#include <hip/hip_runtime.h>
+
+#include "seqcdc_device.h"
+
+namespace seqcdc {
+
+constexpr u32 kSubBytes = 4096;  // input bytes per sub-window: 64 groups, one per lane
+constexpr u32 kRing = 32;        // sub-windows in a chain's LDS ring (128 KiB of input ahead)
+constexpr u32 kBatch = 8;        // producer loads in flight per round
+constexpr u64 kDone = ~0ull;
+
+__device__ __forceinline__ u64 min64(u64 a, u64 b) { return a < b ? a : b; }
+__device__ __forceinline__ u64 max64(u64 a, u64 b) { return a > b ? a : b; }
+__device__ __forceinline__ u64 readfirst64(u64 v) {
+  return (u64)__builtin_amdgcn_readfirstlane((u32)v) | ((u64)__builtin_amdgcn_readfirstlane((u32)(v >> 32)) << 32);
+}
+
+// Position of the k-th (1-based) set bit of a wave-uniform word w: lane b
+// counts the set bits of w below b (mbcnt); the lanes with fewer than k such
+// bits are exactly 0 .. position.
+__device__ __forceinline__ u32 select_bit(u64 w, u32 k) {
+  const u32 below = __builtin_amdgcn_mbcnt_hi((u32)(w >> 32), __builtin_amdgcn_mbcnt_lo((u32)w, 0u));
+  return (u32)__popcll(ballot(below < k)) - 1;
+}
+
+// E (run ends) and O (opposing pairs) of one group from its EO16 dwords.
+__device__ __forceinline__ void unpack_group(const uint4& v, u64& E, u64& O) {
+  E = (u64)__builtin_amdgcn_perm(v.y, v.x, 0x05040100u) | ((u64)__builtin_amdgcn_perm(v.w, v.z, 0x05040100u) << 32);
+  O = (u64)__builtin_amdgcn_perm(v.y, v.x, 0x07060302u) | ((u64)__builtin_amdgcn_perm(v.w, v.z, 0x07060302u) << 32);
+}
+
+// ---------------------------------------------------------------------------
+// Sources of mark bits for a chain
+// ---------------------------------------------------------------------------
+
+struct RingLds {
+  uint4 slot[kRing][64];
+  u64 tag[kRing];  // sub-window held by each slot (kDone = none)
+  u64 want;        // consumer: lowest sub-window still needed; kDone = chain finished
+  u64 item;        // work item handed from thread 0 to both waves
+};
+
+// Reads sub-windows straight from HBM (used for rare re-walks).
+struct DirectSource {
+  const uint4* eo;
+  u64 groups;
+  __device__ __forceinline__ uint4 fetch(u64 sub) {
+    const u64 g = sub * 64 + lane_id();
+    return g < groups ? eo[g] : make_uint4(0, 0, 0, 0);
+  }
+};
+
+// Reads sub-windows straight from HBM and keeps the next one in flight: a
+// chain moves forward about one sub-window per chunk, so the load of the
+// next sub-window overlaps the work on the current one.
+struct PrefetchSource {
+  const uint4* eo;
+  u64 groups;
+  u64 nxt_sub;
+  uint4 nxt;
+  __device__ __forceinline__ uint4 load(u64 sub) {
+    const u64 g = sub * 64 + lane_id();
+    return g < groups ? eo[g] : make_uint4(0, 0, 0, 0);
+  }
+  __device__ __forceinline__ uint4 fetch(u64 sub) {
+    uint4 v;
+    if (sub == nxt_sub) v = nxt;
+    else v = load(sub);
+    nxt_sub = sub + 1;
+    nxt = load(sub + 1);
+    return v;
+  }
+};
+
+// Reads sub-windows from the LDS ring filled by the producer wave.
+struct RingSource {
+  RingLds* r;
+  __device__ __forceinline__ uint4 fetch(u64 sub) {
+    // every lane stores the same value: no divergent branch around the chain's state
+    __hip_atomic_store(&r->want, sub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const u32 slot = (u32)(sub % kRing);
+    for (;;) {
+      u64 t = __hip_atomic_load(&r->tag[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (readfirst64(t) == sub) break;
+      __builtin_amdgcn_s_sleep(1);
+    }
+    return r->slot[slot][lane_id()];
+  }
+};
+
+// Producer wave: keeps the sub-windows [want, want + kRing) of the file in the ring.
+__device__ void ring_producer(RingLds* r, const FileDesc& F) {
+  const u32 lane = lane_id();
+  const uint4* eo = (const uint4*)F.eo;
+  const u64 groups = (F.n + 63) >> 6;
+  const u64 subs = (F.n + kSubBytes - 1) / kSubBytes;
+  u64 next = 0;
+  for (;;) {
+    const u64 w = readfirst64(__hip_atomic_load(&r->want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+    if (w == kDone) return;
+    if (next < w) next = w;  // the consumer jumped ahead
+    const u64 end = min64(w + kRing, subs);
+    if (next >= end) {  // ring full: the consumer needs about one sub-window per chunk
+      __builtin_amdgcn_s_sleep(8);
+      continue;
+    }
+    const u32 cnt = (u32)min64(end - next, kBatch);
+    uint4 v[kBatch];
+#pragma unroll
+    for (u32 i = 0; i < kBatch; i++) {
+      const u64 g = (next + i) * 64 + lane;
+      v[i] = make_uint4(0, 0, 0, 0);
+      if (i < cnt && g < groups) v[i] = eo[g];
+    }
+#pragma unroll
+    for (u32 i = 0; i < kBatch; i++)
+      if (i < cnt) r->slot[(next + i) % kRing][lane] = v[i];
+    if (lane == 0)
+      for (u32 i = 0; i < cnt; i++)
+        __hip_atomic_store(&r->tag[(next + i) % kRing], next + i, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    next += cnt;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The chain
+// ---------------------------------------------------------------------------
+
+template <class Src>
+struct Chain {
+  Src src;
+  u64 n, nblocks;
+  const uint8_t* esum;
+  u64 min_size, max_size;
+  u32 sl, trig, skip;
+  bool skipping;
+  u64 cur;            // sub-window held in E/O (kDone = none)
+  u64 E, O;           // lane l: group cur*64 + l
+  u32 incl;           // lane l: opposing pairs in groups 0..l of the window (inclusive prefix)
+  u32 excl;           // lane l: opposing pairs in groups 0..l-1 of the window
+  u32 fe;             // lane l: first run-end bit of the group (64 = none)
+  u32 total;          // opposing pairs in the whole window
+  u64 emask;          // bit l: group l holds a run end
+  // summary knowledge: blocks [sum_from, sum_to) hold no run end; sum_hit says
+  // whether sum_to is a block with a run end (or the end) rather than a horizon
+  u64 sum_from, sum_to;
+  bool sum_hit, hot;
+};
+
+template <class Src>
+__device__ __forceinline__ void chain_init(Chain<Src>& ch, const FileDesc& F) {
+  ch.n = F.n;
+  ch.nblocks = (F.n + 1023) >> 10;
+  ch.esum = F.esum;
+  ch.min_size = F.min_size;
+  ch.max_size = F.max_size;
+  ch.sl = F.sl;
+  ch.trig = F.trig;
+  ch.skip = F.skip;
+  ch.skipping = F.trig != kNoSkip;
+  ch.cur = kDone;
+  ch.E = ch.O = 0;
+  ch.incl = ch.excl = ch.total = 0;
+  ch.fe = 64;
+  ch.emask = 0;
+  ch.sum_from = ch.sum_to = 0;
+  ch.sum_hit = false;
+  ch.hot = false;
+}
+
+template <class Src>
+__device__ __forceinline__ void ensure(Chain<Src>& ch, u64 sub) {
+  if (ch.cur == sub) return;
+  const uint4 v = ch.src.fetch(sub);
+  unpack_group(v, ch.E, ch.O);
+  ch.cur = sub;
+  // per-window facts every scan of this window reuses
+  ch.emask = ballot(ch.E != 0);
+  ch.fe = ch.E ? ctz64(ch.E) : 64u;
+  if (ch.skipping) {
+    const u32 cnt = (u32)__popcll(ch.O);
+    ch.incl = wave_incl_scan(cnt);
+    ch.excl = ch.incl - cnt;
+    ch.total = readlane(ch.incl, 63);
+  }
+}
+
+// Extend the summary knowledge from block b by one load (1024 blocks, 1 MiB
+// of input): afterwards blocks [b, sum_to) are known to hold no run end.
+template <class Src>
+__device__ void summary_extend(Chain<Src>& ch, u64 b) {
+  const u32 lane = lane_id();
+  const u64 nb = ch.nblocks;
+  u64 to = nb;
+  bool hit = true;
+  if (b < nb) {
+    const u64 a = b & ~15ull;
+    const u64 idx = a + 16ull * lane;
+    // branch-free (keeps the chain state wave-uniform): every lane reads a valid
+    // 16-byte chunk of the padded summary; bytes outside [b, nb) are masked
+    const uint4 v = *(const uint4*)(ch.esum + (idx < nb ? idx : ((nb - 1) & ~15ull)));
+    const u32 d[4] = {v.x, v.y, v.z, v.w};
+    u32 m = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const u32 t = d[k] & 0x01010101u;
+      m |= ((t | (t >> 7) | (t >> 14) | (t >> 21)) & 0xFu) << (4 * k);
+    }
+    const u32 lo_sh = idx < b ? (u32)(b - idx) : 0u;  // < 16, only in lane 0
+    m &= 0xFFFFu << lo_sh;
+    const u64 room = idx < nb ? nb - idx : 0;
+    m = room < 16 ? (m & ((1u << (u32)room) - 1u)) : m;
+    const u64 bal = ballot(m != 0);
+    if (bal) {
+      const u32 l = ctz64(bal);
+      to = a + 16ull * l + (u32)__builtin_ctz(readlane(m, l));
+    } else if (a + 1024 < nb) {
+      to = a + 1024;
+      hit = false;
+    }
+  } else {
+    to = b;
+  }
+  if (!(ch.sum_from <= b && b <= ch.sum_to)) ch.sum_from = b;
+  ch.sum_to = to;
+  ch.sum_hit = hit;
+  ch.hot = true;
+}
+
+// True if no block in [b, ceil(L/1024)) holds a run end, using and extending
+// the summary knowledge.  Cheap when the knowledge already covers b.
+template <class Src>
+__device__ __forceinline__ bool no_end_before(Chain<Src>& ch, u64 b, u64 L) {
+  if (!(ch.sum_from <= b && b <= ch.sum_to)) summary_extend(ch, b);
+  while (!ch.sum_hit && (ch.sum_to << 10) < L) summary_extend(ch, ch.sum_to);
+  return (ch.sum_to << 10) >= L;
+}
+
+// Opposing pairs of the window at positions < pos (0 <= pos <= 4096).
+template <class Src>
+__device__ __forceinline__ u32 opp_before(const Chain<Src>& ch, u32 pos) {
+  if (pos >= kSubBytes) return ch.total;
+  const u32 g = pos >> 6, b = pos & 63;
+  const u32 prior = readlane(ch.excl, g);
+  return b ? prior + (u32)__popcll(readlane64(ch.O, g) & ((1ull << b) - 1ull)) : prior;
+}
+
+// One step over the current sub-window, in byte offsets relative to its
+// start: the first run end at or after er and the need-th opposing pair at or
+// after pr, both before lr.  Returns 0 (neither; `need` reduced by the pairs
+// seen), 1 (run end first, at pos) or 2 (trigger first, at pos).  A pair is
+// never both favourable and opposing, so the two never coincide.  Scalar work
+// on the window's precomputed run-end mask and opposing-pair prefix counts.
+template <class Src>
+__device__ __forceinline__ u32 scan_sub(Chain<Src>& ch, u32 pr, u32 er, u32 lr, u32& need, u32& pos) {
+  const u32 lw = lr < kSubBytes ? lr : kSubBytes;  // scan limit inside this window
+  u32 qe = kSubBytes;                              // first admissible run end (kSubBytes = none)
+  if (er < lw) {
+    const u32 ge = er >> 6;
+    const u64 w = readlane64(ch.E, ge) & (~0ull << (er & 63));
+    if (w) {
+      qe = ge * 64u + ctz64(w);
+    } else {
+      const u64 m = ge < 63 ? (ch.emask & (~0ull << (ge + 1))) : 0ull;
+      if (m) {
+        const u32 g2 = ctz64(m);
+        qe = g2 * 64u + readlane(ch.fe, g2);
+      }
+    }
+    if (qe >= lw) qe = kSubBytes;
+  }
+  if (ch.skipping) {
+    const u32 base = opp_before(ch, pr);
+    const u32 seen = opp_before(ch, qe < kSubBytes ? qe : lw) - base;
+    if (seen >= need) {  // the need-th opposing pair from pr triggers a skip first
+      const u32 target = base + need;
+      const u32 gt = ctz64(ballot(ch.incl >= target));
+      pos = gt * 64u + select_bit(readlane64(ch.O, gt), target - readlane(ch.excl, gt));
+      return 2;
+    }
+    need -= seen;
+  }
+  if (qe < kSubBytes) {
+    pos = qe;
+    return 1;
+  }
+  return 0;
+}
+
+// The cut that follows a cut (or a speculative start) at c.  Wave-uniform.
+// Offsets inside the chunk are 32-bit, relative to c (max_size <= 1 GiB).
+template <class Src>
+__device__ u64 next_cut(Chain<Src>& ch, u64 c) {
+  if (c >= ch.n) return ch.n;  // callers never ask past the end; keeps every loop progressing
+  const u64 rem = ch.n - c;
+  const u32 lim = rem > ch.max_size ? (u32)ch.max_size : (u32)rem;  // Sec. IV limit
+  u32 s = (u32)ch.min_size - ch.sl;                                 // Sec. III-B scan start
+  u32 p = s + 1;                                                    // next pair (p-1, p) to examine
+  u32 e_lo = s + ch.sl - 1;                                         // earliest admissible run end
+  u32 need = ch.trig;                                               // opposing pairs still to the trigger
+  const u32 c32 = (u32)c;
+  for (;;) {
+    if (p >= lim) return c + lim;
+    if (ch.hot) {  // inside a stretch known to hold no run end: nothing to find before the limit?
+      const u64 b = (c + (e_lo > p ? e_lo : p)) >> 10;
+      if (ch.sum_from <= b && b <= ch.sum_to) {
+        if (no_end_before(ch, b, c + lim)) return c + lim;
+      } else {
+        ch.hot = false;
+      }
+    }
+    const u64 sub = (c + p) / kSubBytes;
+    ensure(ch, sub);
+    const u32 w = (u32)(sub * kSubBytes) - c32;  // window start relative to c (mod 2^32)
+    u32 pos = 0;
+    const u32 kind = scan_sub(ch, p - w, (e_lo > p ? e_lo : p) - w, lim - w, need, pos);
+    if (kind == 1) return c + (u32)(pos + w) + 1;  // Sec. III-A: boundary just past the run
+    if (kind == 2) {                             // Sec. III-C: skip SkipSize bytes after the trigger byte
+      const u64 s64 = (u64)(u32)(pos + w) + 1 + ch.skip;  // trigger byte relative to c, then the skip
+      if (s64 >= lim) return c + lim;
+      s = (u32)s64;
+      p = s + 1;
+      e_lo = s + ch.sl - 1;
+      need = ch.trig;
+      continue;
+    }
+    p = w + kSubBytes;
+    if (p >= lim) return c + lim;
+    if (no_end_before(ch, (c + p) >> 10, c + lim)) return c + lim;  // no run end before the limit
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass A: chains from every segment start
+// ---------------------------------------------------------------------------
+
+// Thread 0 takes the next work item and sets the first sub-window the chain
+// will read, so the producer starts streaming at once.
+template <class FirstSub>
+__device__ __forceinline__ bool take_item(RingLds& ring, u32* head, u32 nitems, u64& item, FirstSub first_sub) {
+  for (u32 i = threadIdx.x; i < kRing; i += blockDim.x) ring.tag[i] = kDone;
+  if (threadIdx.x == 0) {
+    const u64 it = atomicAdd(head, 1u);
+    ring.item = it;
+    ring.want = it < nitems ? first_sub((u32)it) : kDone;
+  }
+  __syncthreads();
+  item = readfirst64(ring.item);  // wave-uniform: everything derived from it stays scalar
+  return item < nitems;
+}
+
+__global__ __launch_bounds__(128) void chains_kernel(const FileDesc* __restrict__ files, ChainWs ws,
+                                                     const u32* __restrict__ order, u32 nitems) {
+  __shared__ RingLds ring;
+  const u32 lane = lane_id();
+  const bool consumer = __builtin_amdgcn_readfirstlane(threadIdx.x) < 64;  // wave-uniform role
+  for (;;) {
+    u64 it;
+    auto first_sub = [&](u32 i) -> u64 {
+      const u32 ch = order[i];
+      const FileDesc& G = files[ws.chain_file[ch]];
+      return ((u64)(ch - G.chain0) * G.seg + G.min_size - G.sl + 1) / kSubBytes;
+    };
+    if (!take_item(ring, &ws.counters[0], nitems, it, first_sub)) return;
+    const u32 chain = order[it];
+    const FileDesc& F = files[ws.chain_file[chain]];
+    const u32 k = chain - F.chain0;
+    const u64 S = (u64)k * F.seg;
+    const u64 Send = (k + 1 == F.nseg) ? F.n : S + F.seg;
+    if (consumer) {
+      if (F.n == 0) {
+        *F.out_count = 0;
+      } else {
+        Chain<RingSource> ch;
+        ch.src.r = &ring;
+        chain_init(ch, F);
+        const bool direct = F.nseg == 1;
+        u64* dst = direct ? F.out : ws.list + ws.list_off[chain];
+        const u64 cap = direct ? F.out_cap : ~0ull;
+        u64 cnt = 0, c = S, buf = 0;
+        do {
+          c = next_cut(ch, c);
+          if (lane == (u32)(cnt & 63)) buf = c;
+          cnt++;
+          if ((cnt & 63) == 0 || c >= Send) {  // flush the lanes filled since the last flush
+            const u64 i = ((cnt - 1) & ~63ull) + lane;
+            if (i < cnt && i < cap) dst[i] = buf;
+          }
+        } while (c < Send);
+        if (direct) *F.out_count = cnt;
+        else ws.list_cnt[chain] = (u32)cnt;
+      }
+      __hip_atomic_store(&ring.want, kDone, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+      ring_producer(&ring, F);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass B: continuations
+// ---------------------------------------------------------------------------
+
+// Membership of x in the sorted main part (entries [0, cnt)) of a list,
+// streaming forward (x must not decrease between calls on one cursor).
+struct ListCursor {
+  const u64* list;
+  u32 cnt;
+  u32 base;
+  u64 vals;
+  bool loaded;
+};
+
+__device__ __forceinline__ i32 cursor_find(ListCursor& lc, u64 x) {
+  for (;;) {
+    if (!lc.loaded) {
+      const u32 i = lc.base + lane_id();
+      lc.vals = i < lc.cnt ? lc.list[i] : ~0ull;
+      lc.loaded = true;
+    }
+    const u64 ge = ballot(lc.vals >= x);
+    if (ge == 0) {
+      if (lc.base + 64 < lc.cnt) {
+        lc.base += 64;
+        lc.loaded = false;
+        continue;
+      }
+      return -1;
+    }
+    const u32 fl = ctz64(ge);
+    return readlane64(lc.vals, fl) == x ? (i32)(lc.base + fl) : -1;
+  }
+}
+
+// Continue chain k from its exit cut until one of its cuts is also a cut of
+// the chain that owns that position (or that chain's segment start).
+__global__ __launch_bounds__(128) void continue_kernel(const FileDesc* __restrict__ files, ChainWs ws,
+                                                       const u32* __restrict__ order, u32 nitems) {
+  __shared__ RingLds ring;
+  const u32 lane = lane_id();
+  const bool consumer = __builtin_amdgcn_readfirstlane(threadIdx.x) < 64;  // wave-uniform role
+  for (;;) {
+    u64 it;
+    auto first_sub = [&](u32 i) -> u64 {
+      const u32 ch = order[i];
+      const FileDesc& G = files[ws.chain_file[ch]];
+      const u64 exit_cut = ws.list[ws.list_off[ch] + ws.list_cnt[ch] - 1];
+      return (exit_cut + G.min_size - G.sl + 1) / kSubBytes;
+    };
+    if (!take_item(ring, &ws.counters[1], nitems, it, first_sub)) return;
+    const u32 chain = order[it];
+    const FileDesc& F = files[ws.chain_file[chain]];
+    const u64 n = F.n;
+    const u32 nseg = F.nseg;
+    u64 x = ws.list[ws.list_off[chain] + ws.list_cnt[chain] - 1];  // chain's exit cut
+    if (consumer) {
+      u32 conv_chain = nseg;
+      i32 conv_idx = -1;
+      u32 cc = 0;
+      u64* cont = ws.cont + ws.cont_off[chain];
+      if (x < n) {
+        Chain<RingSource> ch;
+        ch.src.r = &ring;
+        chain_init(ch, F);
+        u32 m = (u32)min64(x / F.seg, nseg - 1);
+        ListCursor lc;
+        auto open = [&](u32 seg) {
+          const u32 cm = F.chain0 + seg;
+          lc.list = ws.list + ws.list_off[cm];
+          lc.cnt = ws.list_cnt[cm] - 1;  // main part: all but the exit cut
+          lc.base = 0;
+          lc.loaded = false;
+        };
+        open(m);
+        for (;;) {
+          const u64 Sm = (u64)m * F.seg;
+          const i32 idx = (x == Sm) ? -1 : cursor_find(lc, x);
+          if (x == Sm || idx >= 0) {
+            conv_chain = m;
+            conv_idx = idx;
+            break;
+          }
+          if (cc < ws.cont_cap) cont[cc] = x;  // uniform condition; every lane stores the same value
+          cc++;
+          x = next_cut(ch, x);
+          if (x >= n) break;  // reached the end of the stream: conv_chain = nseg
+          const u32 m2 = (u32)min64(x / F.seg, nseg - 1);
+          if (m2 != m) {
+            m = m2;
+            open(m);
+          }
+        }
+      }
+      ws.conv_val[chain] = x;
+      ws.conv_chain[chain] = conv_chain;
+      ws.conv_idx[chain] = conv_idx;
+      ws.cont_cnt[chain] = cc;
+      __hip_atomic_store(&ring.want, kDone, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+      ring_producer(&ring, F);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stitch and compaction
+// ---------------------------------------------------------------------------
+
+// Block-wide exclusive scan of one value per thread (256 threads).
+__device__ u64 block_exclusive_scan(u64 v, u64* sh, u64& total) {
+  const u32 t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (u32 d = 1; d < 256; d <<= 1) {
+    u64 a = t >= d ? sh[t - d] : 0;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  total = sh[255];
+  u64 r = sh[t] - v;
+  __syncthreads();
+  return r;
+}
+
+// Stitch (one 256-thread workgroup per multi-segment file): the exact cut
+// sequence starts in chain 0 and moves to chain conv_chain[k] at conv_val[k].
+// Chains strictly between k and conv_chain[k] are covered by k's
+// continuation and contribute nothing.
+__global__ __launch_bounds__(256) void stitch_kernel(const FileDesc* __restrict__ files, ChainWs ws,
+                                                     const u32* __restrict__ multi, u32 nmulti) {
+  __shared__ u64 sh[256];
+  __shared__ u32 s_nj, s_nr;
+  const u32 t = threadIdx.x;
+  const FileDesc& F = files[multi[blockIdx.x]];
+  const u32 nseg = F.nseg, c0 = F.chain0;
+  u32* jumps = ws.jumps + c0;
+  u32* cov = ws.covered + 2 * (u64)c0;
+
+  // 1. boundaries whose continuation skipped at least one whole segment
+  u64 base = 0;
+  for (u32 j0 = 0; j0 < nseg; j0 += 256) {
+    const u32 k = j0 + t;
+    const bool jump = k + 1 < nseg && ws.conv_chain[c0 + k] != k + 1;
+    u64 tot;
+    const u64 pos = block_exclusive_scan(jump ? 1 : 0, sh, tot);
+    if (jump) jumps[base + pos] = k;
+    base += tot;
+  }
+  if (t == 0) s_nj = (u32)base;
+  __syncthreads();
+
+  // 2. walk the jumps in order; a jump from an active chain covers (k, next)
+  if (t == 0) {
+    u32 until = 0, nr = 0;
+    for (u32 i = 0; i < s_nj; i++) {
+      const u32 k = jumps[i];
+      if (k < until) continue;  // k itself is covered
+      const u32 nx = ws.conv_chain[c0 + k];
+      cov[2 * nr] = k + 1;
+      cov[2 * nr + 1] = nx;  // covered: k+1 .. nx-1
+      nr++;
+      until = nx;
+    }
+    s_nr = nr;
+  }
+  __syncthreads();
+  const u32 nr = s_nr;
+
+  // 3. active flags; 4. entry index of each active chain
+  for (u32 j = t; j < nseg; j += 256) {
+    u32 lo = 0, hi = nr;  // first range with start > j
+    while (lo < hi) {
+      u32 mid = (lo + hi) >> 1;
+      if (cov[2 * mid] <= j) lo = mid + 1;
+      else hi = mid;
+    }
+    const bool covered = lo > 0 && j < cov[2 * (lo - 1) + 1];
+    ws.active[c0 + j] = covered ? 0u : 1u;
+    if (j == 0) ws.entry_idx[c0] = 0;
+  }
+  __syncthreads();
+  for (u32 k = t; k + 1 < nseg; k += 256) {
+    if (!ws.active[c0 + k]) continue;
+    const u32 nx = ws.conv_chain[c0 + k];
+    if (nx < nseg) ws.entry_idx[c0 + nx] = ws.conv_idx[c0 + k];
+  }
+  __syncthreads();
+
+  // 5. output count of each chain; 6. offsets
+  base = 0;
+  for (u32 j0 = 0; j0 < nseg; j0 += 256) {
+    const u32 j = j0 + t;
+    u64 cnt = 0;
+    if (j < nseg && ws.active[c0 + j]) {
+      const i32 e = ws.entry_idx[c0 + j];
+      const u64 main_cnt = ws.list_cnt[c0 + j] - 1;
+      const bool last = j + 1 == nseg;
+      cnt = (j > 0 && e < 0 ? 1 : 0) + (main_cnt - (u64)(e > 0 ? e : 0));
+      if (!last) cnt += ws.cont_cnt[c0 + j];
+      if (last || ws.conv_chain[c0 + j] == nseg) cnt += 1;  // the stream end
+    }
+    u64 tot;
+    const u64 pos = block_exclusive_scan(cnt, sh, tot);
+    if (j < nseg) ws.out_off[c0 + j] = base + pos;
+    base += tot;
+  }
+  if (t == 0) *F.out_count = base;
+}
+
+// Compaction: one wave per chain of a multi-segment file copies its exact
+// part; a continuation longer than its buffer is regenerated by walking on.
+__global__ __launch_bounds__(256) void compact_kernel(const FileDesc* __restrict__ files, ChainWs ws,
+                                                      const u32* __restrict__ chains, u32 nchains) {
+  const u32 lane = lane_id();
+  const u32 w = blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
+  if (w >= nchains) return;
+  const u32 chain = chains[w];
+  if (!ws.active[chain]) return;
+  const FileDesc& F = files[ws.chain_file[chain]];
+  const u32 j = chain - F.chain0;
+  const bool last = j + 1 == F.nseg;
+  u64* out = F.out;
+  const u64 cap = F.out_cap;
+  u64 o = ws.out_off[chain];
+  const i32 e = ws.entry_idx[chain];
+  if (j > 0 && e < 0) {
+    if (lane == 0 && o < cap) out[o] = (u64)j * F.seg;
+    o++;
+  }
+  const u64* list = ws.list + ws.list_off[chain];
+  const u64 main_cnt = ws.list_cnt[chain] - 1;
+  for (u64 i = (u64)(e > 0 ? e : 0); i < main_cnt; i += 64) {
+    const u64 ii = i + lane;
+    if (ii < main_cnt && o + (ii - i) < cap) out[o + (ii - i)] = list[ii];
+    o += (main_cnt - i < 64) ? main_cnt - i : 64;
+  }
+  if (!last) {
+    const u32 cc = ws.cont_cnt[chain];
+    const u32 stored = cc < ws.cont_cap ? cc : ws.cont_cap;
+    const u64* cont = ws.cont + ws.cont_off[chain];
+    for (u32 i = 0; i < stored; i += 64) {
+      const u32 ii = i + lane;
+      if (ii < stored && o + (ii - i) < cap) out[o + (ii - i)] = cont[ii];
+      o += (stored - i < 64) ? stored - i : 64;
+    }
+    if (cc > stored) {
+      Chain<DirectSource> ch;
+      ch.src.eo = (const uint4*)F.eo;
+      ch.src.groups = (F.n + 63) >> 6;
+      chain_init(ch, F);
+      u64 x = cont[stored - 1];
+      for (u32 i = stored; i < cc; i++) {
+        x = next_cut(ch, x);
+        if (lane == 0 && o < cap) out[o] = x;
+        o++;
+      }
+    }
+  }
+  if (last || ws.conv_chain[chain] == F.nseg) {
+    if (lane == 0 && o < cap) out[o] = F.n;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_chains(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32 groups,
+                         hipStream_t st) {
+  if (!nitems) return hipSuccess;
+  hipLaunchKernelGGL(chains_kernel, dim3(groups), dim3(128), 0, st, d_files, ws, d_order, nitems);
+  return hipGetLastError();
+}
+
+hipError_t launch_continue(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32 groups,
+                           hipStream_t st) {
+  if (!nitems) return hipSuccess;
+  hipLaunchKernelGGL(continue_kernel, dim3(groups), dim3(128), 0, st, d_files, ws, d_order, nitems);
+  return hipGetLastError();
+}
+
+hipError_t launch_stitch(const FileDesc* d_files, const ChainWs& ws, const u32* d_multi, u32 nmulti, hipStream_t st) {
+  if (!nmulti) return hipSuccess;
+  hipLaunchKernelGGL(stitch_kernel, dim3(nmulti), dim3(256), 0, st, d_files, ws, d_multi, nmulti);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const FileDesc* d_files, const ChainWs& ws, const u32* d_chains, u32 nchains,
+                          hipStream_t st) {
+  if (!nchains) return hipSuccess;
+  const u32 groups = (nchains + kWavesPerGroup - 1) / kWavesPerGroup;
+  hipLaunchKernelGGL(compact_kernel, dim3(groups), dim3(256), 0, st, d_files, ws, d_chains, nchains);
+  return hipGetLastError();
+}
+
+}  // namespace seqcdc

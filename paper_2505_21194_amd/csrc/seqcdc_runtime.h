@@ -48,7 +48,7 @@ struct Plan {
   u32 cus = 256;
   std::string arch;
   std::mutex mu;
-  DevBuf eo, list, cont, chains, tables, misc;
+  DevBuf eo, esum, list, cont, chains, tables, misc;
   HostBuf staging, readback;
   hipEvent_t call_done = nullptr, upload_done = nullptr;
   bool pending = false, upload_pending = false;

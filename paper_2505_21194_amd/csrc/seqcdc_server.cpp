@@ -92,9 +92,6 @@ static int launch_pass(Server* s, Pass* ps) {
   if ((rc = ps->d_counts.reserve(nf * 8))) return rc;
   if ((rc = ps->h_cuts.reserve(total * 8))) return rc;
   if ((rc = ps->h_counts.reserve(nf * 8))) return rc;
-  {
-    std::lock_guard<std::mutex> g(ps->plan.mu);
-  }
   rc = chunk_batch(&ps->plan, files.data(), nf, s->params.data(), (u32)s->params.size(), (u64*)ps->d_cuts.p,
                    ps->offs.data(), (u64*)ps->d_counts.p, ps->stream);
   if (rc) return rc;
@@ -138,27 +135,23 @@ static void scheduler(Server* s) {
   for (;;) {
     // 1. retire finished passes
     bool any_busy = false;
-    for (Pass* ps : s->passes) {
-      if (!ps->busy) continue;
-      hipError_t q = hipEventQuery(ps->done);
-      if (q == hipSuccess) finish_pass(s, ps, SEQCDC_OK);
-      else if (q == hipErrorNotReady) any_busy = true;
-      else finish_pass(s, ps, SEQCDC_EHIP);
-    }
-    // 2. admit a group into a free pass
     Pass* free_pass = nullptr;
-    for (Pass* ps : s->passes)
-      if (!ps->busy) {
-        free_pass = ps;
-        break;
+    for (Pass* ps : s->passes) {
+      if (ps->busy) {
+        hipError_t q = hipEventQuery(ps->done);
+        if (q == hipSuccess) finish_pass(s, ps, SEQCDC_OK);
+        else if (q != hipErrorNotReady) finish_pass(s, ps, SEQCDC_EHIP);
       }
-    bool launched = false;
+      if (ps->busy) any_busy = true;
+      else if (!free_pass) free_pass = ps;
+    }
+    // 2. admit a group of queued requests into the free pass
+    std::vector<Request*> group;
+    u64 group_bytes = 0;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       if (s->stop && s->queue.empty() && !any_busy) return;
-      if (free_pass && !s->queue.empty()) {
-        std::vector<Request*> group;
-        u64 group_bytes = 0;
+      if (free_pass) {
         for (auto it = s->queue.begin(); it != s->queue.end() && group.size() < s->cfg.max_batch;) {
           Request* r = *it;
           const bool fits = s->bytes_inflight + group_bytes + r->cost <= s->cfg.budget_bytes &&
@@ -173,35 +166,26 @@ static void scheduler(Server* s) {
             ++it;
           }
         }
-        if (!group.empty()) {
-          const auto now = Clock::now();
-          for (Request* r : group) r->t_admit = now;
-          s->bytes_inflight += group_bytes;
-          s->reqs_inflight += group.size();
-          s->stat_admitted += group.size();
-          s->stat_passes++;
-          s->stat_peak_bytes = std::max(s->stat_peak_bytes, s->bytes_inflight);
-          s->stat_peak_reqs = std::max(s->stat_peak_reqs, s->reqs_inflight);
-          free_pass->reqs = group;
-          free_pass->bytes = group_bytes;
-          lk.unlock();
-          int rc = launch_pass(s, free_pass);
-          if (rc) finish_pass(s, free_pass, rc);
-          launched = true;
-        }
       }
-      if (!launched) {
-        lk = std::unique_lock<std::mutex>(s->mu, std::try_to_lock);
+      if (group.empty()) {
+        // 3. idle: poll the GPU briefly while passes run, else sleep until a submission
+        if (any_busy) s->cv_sched.wait_for(lk, std::chrono::microseconds(20));
+        else s->cv_sched.wait_for(lk, std::chrono::milliseconds(2));
+        continue;
       }
+      const auto now = Clock::now();
+      for (Request* r : group) r->t_admit = now;
+      s->bytes_inflight += group_bytes;
+      s->reqs_inflight += group.size();
+      s->stat_admitted += group.size();
+      s->stat_passes++;
+      s->stat_peak_bytes = std::max(s->stat_peak_bytes, s->bytes_inflight);
+      s->stat_peak_reqs = std::max(s->stat_peak_reqs, s->reqs_inflight);
     }
-    if (launched) continue;
-    // 3. idle: wait for a submission, or poll the GPU briefly while passes run
-    std::unique_lock<std::mutex> lk(s->mu);
-    if (any_busy) {
-      s->cv_sched.wait_for(lk, std::chrono::microseconds(20));
-    } else if (!s->stop && (s->queue.empty() || !free_pass)) {
-      s->cv_sched.wait_for(lk, std::chrono::milliseconds(2));
-    }
+    free_pass->reqs = group;
+    free_pass->bytes = group_bytes;
+    int rc = launch_pass(s, free_pass);
+    if (rc) finish_pass(s, free_pass, rc);
   }
 }
 
