@@ -80,14 +80,25 @@ int seqcdc_plan_create(int device, seqcdc_plan** out);
 int seqcdc_plan_destroy(seqcdc_plan* plan);
 
 /* Tuning knobs of a plan (0 = keep).  segment_bytes: length of the segments
- * a stream is split into for speculative resolution (rounded up to 4 KiB);
- * mark_span_blocks: 1 KiB blocks per mark wave (4, 8 or 16); waves_per_cu:
- * resident waves per compute unit of the persistent resolve kernels. */
+ * a stream is split into for speculative resolution (rounded up to a whole
+ * number of mark spans); mark_span_blocks: 1 KiB blocks per mark span, the
+ * unit of marking work (4, 8, 16, 32 or 64); waves_per_cu: waves per compute
+ * unit of the persistent chain kernels, one chain per wave (4..32, a
+ * multiple of 4). */
 int seqcdc_plan_set_tuning(seqcdc_plan* plan, uint64_t segment_bytes, uint32_t mark_span_blocks,
                            uint32_t waves_per_cu);
 /* Current choices for a stream of n bytes under p. */
 int seqcdc_plan_get_tuning(seqcdc_plan* plan, uint64_t n, const seqcdc_params* p, uint64_t* segment_bytes,
                            uint32_t* mark_span_blocks, uint32_t* waves_per_cu);
+
+/* Per-phase timing of the plan's calls (off by default; on adds HIP events
+ * to every call).  seqcdc_plan_phase_ms waits for the plan's last timed call
+ * and writes 4 durations in milliseconds: the mark kernel (with the clearing
+ * of two work counters before it), pass A (speculative chains), pass B
+ * (continuations) and stitch + compaction (the last two are 0 when no stream
+ * had more than one segment).  SEQCDC_EINVAL if no timed call was made. */
+int seqcdc_plan_set_timing(seqcdc_plan* plan, int on);
+int seqcdc_plan_phase_ms(seqcdc_plan* plan, float* ms4);
 
 /* Autotuner: time candidate segment sizes, mark spans and resolve occupancies
  * on the given device-resident sample stream, keep the fastest in the plan and
@@ -117,8 +128,9 @@ typedef struct {
 } seqcdc_file;
 
 /* Chunk many independent device-resident files in one pass: one mark launch
- * over all files, a persistent work-stealing resolve over (file, segment)
- * items (largest first), then stitching and compaction.
+ * over all files, one persistent launch of speculative chains over every
+ * (file, segment) (largest first), then continuations, stitching and
+ * compaction.
  * h_cut_offsets: host array of nfiles+1 offsets; file f's cuts go to
  *   d_cuts[h_cut_offsets[f] ..], and each range must hold at least
  *   seqcdc_max_cuts(n_f, params) entries (checked; SEQCDC_EINVAL otherwise).

@@ -66,6 +66,8 @@ _SIGS = {
     "seqcdc_plan_create": ([ctypes.c_int, ctypes.POINTER(_p)], ctypes.c_int),
     "seqcdc_plan_destroy": ([_p], ctypes.c_int),
     "seqcdc_plan_set_tuning": ([_p, _u64, _u32, _u32], ctypes.c_int),
+    "seqcdc_plan_set_timing": ([_p, ctypes.c_int], ctypes.c_int),
+    "seqcdc_plan_phase_ms": ([_p, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "seqcdc_plan_get_tuning": ([_p, _u64, ctypes.POINTER(seqcdc_params), ctypes.POINTER(_u64),
                                 ctypes.POINTER(_u32), ctypes.POINTER(_u32)], ctypes.c_int),
     "seqcdc_autotune": ([_p, _p, _u64, ctypes.POINTER(seqcdc_params), ctypes.POINTER(ctypes.c_double), _p],
@@ -156,6 +158,17 @@ def seqcdc_plan_destroy(plan):
 
 def seqcdc_plan_set_tuning(plan, segment_bytes=0, mark_span_blocks=0, waves_per_cu=0):
     _check(lib.seqcdc_plan_set_tuning(plan, segment_bytes, mark_span_blocks, waves_per_cu))
+
+
+def seqcdc_plan_set_timing(plan, on=True):
+    _check(lib.seqcdc_plan_set_timing(plan, 1 if on else 0))
+
+
+def seqcdc_plan_phase_ms(plan):
+    """Durations (ms) of the last timed call: mark, pass A, pass B, stitch + compaction."""
+    ms = (ctypes.c_float * 4)()
+    _check(lib.seqcdc_plan_phase_ms(plan, ms))
+    return tuple(ms)
 
 
 def seqcdc_plan_get_tuning(plan, n, params):

@@ -1,6 +1,6 @@
 // C ABI of libseqcdc: parameter checks, plans (device workspaces + pinned
 // staging), batch preparation and the launch sequence
-//   mark -> chains -> [continuations -> stitch -> compact]
+//   mark -> pass A chains -> [pass B continuations -> stitch -> compact]
 // for the plain (one stream) and batched (many files) entry points.
 #include <hip/hip_runtime.h>
 
@@ -18,12 +18,12 @@
 
 namespace seqcdc {
 
-hipError_t launch_mark(const FileDesc* d_files, u32 nfiles, u64 total_spans, u32 span_blocks, u32* d_counters,
-                       hipStream_t st);
-hipError_t launch_chains(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32 groups,
-                         hipStream_t st);
-hipError_t launch_continue(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32 groups,
-                           hipStream_t st);
+hipError_t launch_mark(const FileDesc* d_files, u32 nfiles, u64 total_spans, u32 span_blocks, hipStream_t st);
+hipError_t launch_clear(u32* p, u32 count, hipStream_t st);
+hipError_t launch_chains(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32* head,
+                         u32 groups, hipStream_t st);
+hipError_t launch_continue(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32* head,
+                           u32 groups, hipStream_t st);
 hipError_t launch_stitch(const FileDesc* d_files, const ChainWs& ws, const u32* d_multi, u32 nmulti,
                          hipStream_t st);
 hipError_t launch_compact(const FileDesc* d_files, const ChainWs& ws, const u32* d_chains, u32 nchains,
@@ -167,21 +167,21 @@ u64 Plan::segment_for(u64 n, const seqcdc_params* p) const {
   }
   seg = std::max<u64>(seg, 64 * 1024);
   if (n / seg > kMaxSegments) seg = n / kMaxSegments + 1;
-  return round_up(seg, 4096);
+  return round_up(seg, (u64)span_blocks_for(p) * kMarkBlock);  // segments start on span boundaries
 }
 
 u32 Plan::span_blocks_for(const seqcdc_params* p) const {
   if (span_override) return span_override;
   TuneEntry te;
   if (p && tune_lookup(plan_key(this, p), &te)) return te.span_blocks;
-  return 8;
+  return 16;
 }
 
 u32 Plan::waves_for(const seqcdc_params* p) const {
   if (waves_override) return waves_override;
   TuneEntry te;
   if (p && tune_lookup(plan_key(this, p), &te)) return te.waves_per_cu;
-  return 8;
+  return 32;
 }
 
 // ---------------------------------------------------------------- plans
@@ -201,9 +201,11 @@ int plan_init(Plan* pl, int device) {
 
 void plan_free(Plan* pl) {
   if (pl->pending) (void)hipEventSynchronize(pl->call_done);
-  for (DevBuf* b : {&pl->eo, &pl->esum, &pl->list, &pl->cont, &pl->chains, &pl->tables, &pl->misc}) b->release();
+  for (DevBuf* b : {&pl->eo, &pl->esum, &pl->list, &pl->cont, &pl->chains, &pl->tables, &pl->flags, &pl->misc}) b->release();
   pl->staging.release();
   pl->readback.release();
+  for (hipEvent_t& e : pl->tev)
+    if (e) (void)hipEventDestroy(e);
   if (pl->call_done) (void)hipEventDestroy(pl->call_done);
   if (pl->upload_done) (void)hipEventDestroy(pl->upload_done);
 }
@@ -230,6 +232,16 @@ static size_t carve_size(std::initializer_list<size_t> parts) {
   size_t s = 0;
   for (size_t x : parts) s += round_up(x, 256) + 256;
   return s;
+}
+
+static hipError_t timing_mark(Plan* pl, int i, hipStream_t st) {
+  if (!pl->timing) return hipSuccess;
+  if (!pl->tev[i]) {
+    hipError_t e = hipEventCreate(&pl->tev[i]);
+    if (e != hipSuccess) return e;
+  }
+  pl->timed = i == 4;
+  return hipEventRecord(pl->tev[i], st);
 }
 
 // Prepare and enqueue the whole pipeline for `specs` on `st`.
@@ -274,14 +286,14 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
     d.out_count = s.out_count;
     if (d.nseg > 1) {
       multi.push_back(f);
-      cont_cap = std::max<u32>(cont_cap, (u32)std::min<u64>(2 * d.seg / d.min_size + 64, 4096));
+      cont_cap = std::max<u32>(cont_cap, (u32)std::max<u64>(1024, std::min<u64>(2 * d.seg / d.min_size + 64, 4096)));
     }
   }
   if (mark_only) {
     fd[0].eo = (u32*)specs[0].out;
   }
 
-  // chain tables
+  // chain tables; pass A takes the chains largest segment first
   std::vector<u32> chain_file(nchains);
   std::vector<u64> list_off(nchains, 0), cont_off(nchains, 0);
   std::vector<u32> order(nchains), border, compact;
@@ -322,7 +334,7 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
       carve_size({nfiles * sizeof(FileDesc), nchains * 4ull, nchains * 8ull, nchains * 8ull, nchains * 4ull,
                   border.size() * 4 + 4, multi.size() * 4 + 4, compact.size() * 4 + 4});
   if ((rc = pl->tables.reserve(table_bytes))) return rc;
-  if ((rc = pl->misc.reserve(4096))) return rc;
+  if ((rc = pl->flags.reserve(256))) return rc;  // work counters of pass A and pass B
 
   // assign device pointers
   for (u32 f = 0; f < nfiles; f++) {
@@ -362,7 +374,6 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   pl->upload_pending = true;
 
   const FileDesc* d_files = (const FileDesc*)dev(h_files);
-  u32* d_counters = (u32*)pl->misc.p;
 
   // ---- chain workspace
   ChainWs ws;
@@ -383,22 +394,31 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   ws.jumps = carve<u32>(cc, nchains);
   ws.out_off = carve<u64>(cc, nchains);
   ws.covered = (u32*)carve<u64>(cc, nchains);
-  ws.counters = d_counters;
 
   // ---- launches
-  HIP_TRY(launch_mark(d_files, nfiles, spans, U, d_counters, st));
-  if (!mark_only) {
-    // one chain per two-wave workgroup; at most 4 ring workgroups fit a CU's LDS
-    const u32 resident = std::max<u32>(1, pl->cus * std::min<u32>(4, std::max<u32>(1, waves / 2)));
-    const u32 g_chains = std::min<u32>(nchains, resident);
-    HIP_TRY(launch_chains(d_files, ws, (const u32*)dev(h_order), nchains, g_chains, st));
+  u32* heads = (u32*)pl->flags.p;
+  if (mark_only) {
+    HIP_TRY(launch_mark(d_files, nfiles, spans, U, st));
+  } else {
+    const u32 groups = std::max<u32>(1, pl->cus * waves / kWavesPerGroup);  // 4 independent waves each
+    HIP_TRY(timing_mark(pl, 0, st));
+    HIP_TRY(launch_clear(heads, 2, st));
+    HIP_TRY(launch_mark(d_files, nfiles, spans, U, st));
+    HIP_TRY(timing_mark(pl, 1, st));
+    HIP_TRY(launch_chains(d_files, ws, (const u32*)dev(h_order), nchains, heads, std::min<u32>(groups, (nchains + 3) / 4),
+                          st));
+    HIP_TRY(timing_mark(pl, 2, st));
     if (!multi.empty()) {
       const u32 nb = (u32)border.size();
-      const u32 g_b = std::min<u32>(nb, resident);
-      HIP_TRY(launch_continue(d_files, ws, (const u32*)dev(h_border), nb, std::max<u32>(g_b, 1), st));
+      HIP_TRY(launch_continue(d_files, ws, (const u32*)dev(h_border), nb, heads + 1,
+                              std::max<u32>(1, std::min<u32>(groups, (nb + 3) / 4)), st));
+      HIP_TRY(timing_mark(pl, 3, st));
       HIP_TRY(launch_stitch(d_files, ws, (const u32*)dev(h_multi), (u32)multi.size(), st));
       HIP_TRY(launch_compact(d_files, ws, (const u32*)dev(h_compact), (u32)compact.size(), st));
+    } else {
+      HIP_TRY(timing_mark(pl, 3, st));
     }
+    HIP_TRY(timing_mark(pl, 4, st));
   }
   HIP_TRY(hipEventRecord(pl->call_done, st));
   pl->pending = true;
@@ -532,13 +552,33 @@ int seqcdc_plan_set_tuning(seqcdc_plan* plan, uint64_t segment_bytes, uint32_t m
                            uint32_t waves_per_cu) {
   if (!plan) return fail(SEQCDC_EINVAL, "plan is NULL");
   Plan* pl = (Plan*)plan;
-  if (mark_span_blocks && mark_span_blocks != 4 && mark_span_blocks != 8 && mark_span_blocks != 16)
-    return fail(SEQCDC_EINVAL, "mark_span_blocks must be 4, 8 or 16");
-  if (waves_per_cu > 32) return fail(SEQCDC_EINVAL, "waves_per_cu must be <= 32");
+  if (mark_span_blocks && mark_span_blocks != 4 && mark_span_blocks != 8 && mark_span_blocks != 16 &&
+      mark_span_blocks != 32 && mark_span_blocks != 64)
+    return fail(SEQCDC_EINVAL, "mark_span_blocks must be 4, 8, 16, 32 or 64");
+  if (waves_per_cu > 32 || waves_per_cu % 4) return fail(SEQCDC_EINVAL, "waves_per_cu must be a multiple of 4, <= 32");
   std::lock_guard<std::mutex> g(pl->mu);
   if (segment_bytes) pl->seg_override = segment_bytes;
   if (mark_span_blocks) pl->span_override = mark_span_blocks;
   if (waves_per_cu) pl->waves_override = waves_per_cu;
+  return SEQCDC_OK;
+}
+
+int seqcdc_plan_set_timing(seqcdc_plan* plan, int on) {
+  if (!plan) return fail(SEQCDC_EINVAL, "plan is NULL");
+  Plan* pl = (Plan*)plan;
+  std::lock_guard<std::mutex> g(pl->mu);
+  pl->timing = on != 0;
+  pl->timed = false;
+  return SEQCDC_OK;
+}
+
+int seqcdc_plan_phase_ms(seqcdc_plan* plan, float* ms4) {
+  if (!plan || !ms4) return fail(SEQCDC_EINVAL, "NULL argument");
+  Plan* pl = (Plan*)plan;
+  std::lock_guard<std::mutex> g(pl->mu);
+  if (!pl->timed) return fail(SEQCDC_EINVAL, "no timed call on this plan");
+  HIP_TRY(hipEventSynchronize(pl->tev[4]));
+  for (int i = 0; i < 4; i++) HIP_TRY(hipEventElapsedTime(&ms4[i], pl->tev[i], pl->tev[i + 1]));
   return SEQCDC_OK;
 }
 

@@ -1,5 +1,5 @@
 // Autotuner: picks the segment length of speculative resolution, the mark
-// span and the resident waves of the persistent resolve kernels by timing
+// span and the waves per CU of the persistent chain kernels by timing
 // candidates on a device-resident sample.  Every candidate produces the same
 // cuts; only speed differs.  Results go to a process-wide cache keyed by
 // (arch, CU count, SeqLength, average class).
@@ -75,18 +75,18 @@ extern "C" int seqcdc_autotune(seqcdc_plan* plan, const void* d_sample, uint64_t
     }
     return SEQCDC_OK;
   };
-  // coordinate search: segment length, then mark span, then resolve occupancy
+  // coordinate search: segment length, then mark span, then chain occupancy
   for (u64 m : {32ull, 64ull, 128ull, 256ull, 512ull, 1024ull})
-    if ((rc = trial(m, 8, 8))) break;
+    if ((rc = trial(m, 16, 32))) break;
   if (!rc) {
     const u64 m = best.seg_mult;
-    for (u32 s : {4u, 16u})
-      if ((rc = trial(m, s, 8))) break;
+    for (u32 s : {8u, 32u, 64u})
+      if ((rc = trial(m, s, 32))) break;
   }
   if (!rc) {
     const u64 m = best.seg_mult;
     const u32 s = best.span_blocks;
-    for (u32 w : {2u, 4u, 16u})
+    for (u32 w : {8u, 16u, 24u})
       if ((rc = trial(m, s, w))) break;
   }
   pl->seg_override = saved_seg;

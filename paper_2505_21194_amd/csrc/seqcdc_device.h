@@ -34,9 +34,11 @@ __device__ __forceinline__ u32 wave_incl_scan(u32 v) {
   return v;
 }
 
+// Takes the next index of a work counter for the whole wave.  Every lane
+// executes the atomic (lane 0 adds 1, the others 0), so no branch surrounds it
+// and the value lane 0 receives is read back in the same straight-line code.
 __device__ __forceinline__ u32 wave_pop(u32* head) {
-  u32 v = 0;
-  if (lane_id() == 0) v = atomicAdd(head, 1u);
+  const u32 v = atomicAdd(head, lane_id() == 0 ? 1u : 0u);
   return __builtin_amdgcn_readfirstlane(v);
 }
 

@@ -29,7 +29,7 @@ struct FileDesc {
   u64 min_size, max_size;
   u32 trig;             // SkipTrigger, kNoSkip = off
   u32 skip;             // SkipSize
-  u64 mark_span0;       // first mark wave of this file
+  u64 mark_span0;       // global index of the file's first mark span
   u64 seg;              // segment length for speculative chains
   u32 nseg;             // number of segments (chains)
   u32 chain0;           // global index of chain 0 of this file
@@ -56,7 +56,6 @@ struct ChainWs {
   u64* out_off;        // stitch: output offset of the chain's part
   u32* jumps;          // stitch scratch: boundaries whose continuation passed a whole segment
   u32* covered;        // stitch scratch: covered ranges (pairs)
-  u32* counters;       // [0] chain queue head, [1] boundary queue head
 };
 
 }  // namespace seqcdc

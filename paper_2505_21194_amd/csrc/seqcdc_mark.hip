@@ -1,224 +1,28 @@
-// SeqCDC mark step on CDNA4 (gfx950).
-//
-// The method (Udayashankar & Al-Kiswany, arXiv 2505.21194): a chunk ends
-// right after the first run of SeqLength strictly monotone bytes (Sec.
-// III-A) found at or after min - SeqLength bytes into the chunk (Sec.
-// III-B); after SkipTrigger opposing pairs the next SkipSize bytes are not
-// scanned and the counters restart (Sec. III-C); a chunk never exceeds the
-// maximum size (Sec. IV).
-//
-// Mark (the vector formulation of Sec. III-D, one wave per 1 KiB step): every
-// byte pair becomes one favourable bit F and one opposing bit O; E, the AND of
-// SeqLength-1 shifted F masks, marks the bytes that end a candidate run.  The
-// bits are written packed (EO16), plus one summary byte per 1 KiB block that
-// says whether the block holds any run end.
+// SeqCDC mark step on CDNA4 (gfx950): the stand-alone mark kernel, which
+// writes the EO16 bitmaps of a stream without resolving cuts.  The chunking
+// entry points mark inside the pipeline kernel instead, with the same device
+// functions.
 
 #include <hip/hip_runtime.h>
 
-#include "seqcdc_device.h"
+#include "seqcdc_mark.h"
 
 namespace seqcdc {
 
-// ---------------------------------------------------------------------------
-// Mark
-// ---------------------------------------------------------------------------
-
-// Per-halfword unsigned difference; bit 15 / bit 31 is set iff a < b.
-__device__ __forceinline__ u32 sub16x2(u32 a, u32 b) {
-  us2 va = __builtin_bit_cast(us2, a), vb = __builtin_bit_cast(us2, b);
-  return __builtin_bit_cast(u32, (us2)(va - vb));
-}
-
-// Four 0x00/0xFF byte masks (one dword per 4 input bytes, in byte order) ->
-// 16 bits, bit i = byte i.
-__device__ __forceinline__ u32 pack16(u32 m0, u32 m1, u32 m2, u32 m3) {
-  const u32 sel = 0x88442211u;  // byte j keeps bit j (from the low dword) and bit 4+j (high dword)
-  u32 t01 = ((m0 & 0x0F0F0F0Fu) | (m1 & 0xF0F0F0F0u)) & sel;
-  u32 t23 = ((m2 & 0x0F0F0F0Fu) | (m3 & 0xF0F0F0F0u)) & sel;
-  u32 hi = __builtin_amdgcn_sad_u8(t23, 0u, 0u);  // sum of bytes = OR of disjoint bits
-  return __builtin_amdgcn_sad_u8(t01, 0u, hi << 8);
-}
-
-// For the 16 bytes x[0..3] (little endian) preceded by byte `prev`:
-// up16 bit i = byte i > its predecessor, down16 bit i = byte i < its predecessor.
-__device__ __forceinline__ void compare16(const u32 x[4], u32 prev, u32& up16, u32& down16) {
-  u32 mu[4], md[4];
-#pragma unroll
-  for (int k = 0; k < 4; k++) {
-    u32 before = k ? x[k - 1] : (prev << 24);
-    u32 xe = x[k] & 0x00FF00FFu;                                   // bytes 0, 2
-    u32 xo = (x[k] >> 8) & 0x00FF00FFu;                            // bytes 1, 3
-    u32 pe = __builtin_amdgcn_perm(x[k], before, 0x0c050c03u);     // predecessors of bytes 0, 2
-    // predecessors of bytes 1, 3 are bytes 0, 2 (= xe)
-    u32 up_e = sub16x2(pe, xe), up_o = sub16x2(xe, xo);
-    u32 dn_e = sub16x2(xe, pe), dn_o = sub16x2(xo, xe);
-    // gather the four sign bits in byte order as 0x00/0xFF bytes
-    mu[k] = __builtin_amdgcn_perm(up_o, up_e, 0x0B090A08u);
-    md[k] = __builtin_amdgcn_perm(dn_o, dn_e, 0x0B090A08u);
-  }
-  up16 = pack16(mu[0], mu[1], mu[2], mu[3]);
-  down16 = pack16(md[0], md[1], md[2], md[3]);
-}
-
-// Bits 16..31 of the AND of (len) consecutive bits ending at each position of
-// ext = (cur16 << 16) | prev16, i.e. which of the 16 current bytes end a run of
-// `len` favourable pairs.
-__device__ __forceinline__ u32 run_ends16(u32 cur16, u32 prev16, u32 len) {
-  u32 r = (cur16 << 16) | prev16;
-  u32 have = 1;
-  while (have < len) {
-    u32 sh = have < len - have ? have : len - have;
-    r &= r << sh;
-    have += sh;
-  }
-  return r >> 16;
-}
-
-// 16 bytes starting `r` (0..15) bytes into the aligned 32 bytes (lo, hi).
-__device__ __forceinline__ void funnel16(const uint4& lo, const uint4& hi, u32 r, u32 x[4]) {
-  u32 d[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-  u32 a = r >> 2, b = r & 3;
-#pragma unroll
-  for (int k = 0; k < 4; k++) {
-    u32 w0 = d[k], w1 = d[k + 1], w2 = d[k + 2], w3 = d[k + 3], w4 = d[k + 4];
-    u32 l0 = a == 0 ? w0 : a == 1 ? w1 : a == 2 ? w2 : w3;
-    u32 l1 = a == 0 ? w1 : a == 1 ? w2 : a == 2 ? w3 : w4;
-    x[k] = __builtin_amdgcn_alignbyte(l1, l0, b);
-  }
-}
-
-// Load the 16 bytes of this lane for the 1 KiB block at file offset B.  All
-// loads are 16-byte aligned: a 16-byte aligned chunk never straddles a page,
-// so chunks that overlap the stream [data, data+n) are safe to read whole;
-// bytes outside the stream are ignored by the caller.
-__device__ __forceinline__ void load_block(const uint8_t* data, u64 n, u64 B, u32 x[4]) {
-  const u32 lane = lane_id();
-  const uintptr_t addr = (uintptr_t)data;
-  const u32 r = (u32)(addr & 15);
-  const uint4* base = (const uint4*)(addr - r);  // aligned view; byte q of the stream is at r + q
-  const u64 first = (B >> 4) + lane;              // aligned chunk index of this lane
-  const u64 end_chunk = (r + n + 15) >> 4;        // aligned chunks overlapping the stream
-  uint4 lo = make_uint4(0, 0, 0, 0);
-  if (first < end_chunk) {
-    u32x4 v = __builtin_nontemporal_load((const u32x4*)(base + first));
-    lo = make_uint4(v.x, v.y, v.z, v.w);
-  }
-  if (r == 0) {
-    x[0] = lo.x; x[1] = lo.y; x[2] = lo.z; x[3] = lo.w;
-    return;
-  }
-  uint4 hi;
-  hi.x = __shfl_down(lo.x, 1);
-  hi.y = __shfl_down(lo.y, 1);
-  hi.z = __shfl_down(lo.z, 1);
-  hi.w = __shfl_down(lo.w, 1);
-  if (lane == 63) {
-    hi = make_uint4(0, 0, 0, 0);
-    if (first + 1 < end_chunk) hi = base[first + 1];
-  }
-  funnel16(lo, hi, r, x);
-}
-
-// 16 bytes at file offset B-16 (B >= 16) for the halo, wave-uniform.
-__device__ __forceinline__ void load_halo(const uint8_t* data, u64 n, u64 B, u32 x[4]) {
-  const uintptr_t addr = (uintptr_t)data;
-  const u32 r = (u32)(addr & 15);
-  const uint4* base = (const uint4*)(addr - r);
-  const u64 c0 = (B - 16) >> 4;
-  uint4 lo = base[c0];
-  if (r == 0) {
-    x[0] = lo.x; x[1] = lo.y; x[2] = lo.z; x[3] = lo.w;
-    return;
-  }
-  uint4 hi = base[c0 + 1];  // overlaps byte B-1 < n, so it overlaps the stream
-  funnel16(lo, hi, r, x);
-}
-
-// One wave marks `U` consecutive 1 KiB blocks of one file.  Files are located
-// by a binary search over their first mark span.
-template <int U>
+// One wave per mark span; files are located by a binary search over their
+// first span.
 __global__ __launch_bounds__(256) void mark_kernel(const FileDesc* __restrict__ files, u32 nfiles, u64 total_spans,
-                                                   u32* __restrict__ counters) {
-  const u32 lane = lane_id();
-  const u64 span = (u64)blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
-  if (blockIdx.x == 0 && threadIdx.x < 2) counters[threadIdx.x] = 0;  // queue heads of the resolve kernels
+                                                   u32 span_blocks) {
+  const u64 span = (u64)blockIdx.x * kWavesPerGroup + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   if (span >= total_spans) return;
-  u32 lo = 0, hi = nfiles;
-  while (hi - lo > 1) {
-    u32 mid = (lo + hi) >> 1;
-    if (files[mid].mark_span0 <= span) lo = mid;
-    else hi = mid;
-  }
-  const FileDesc& F = files[lo];
-  const uint8_t* data = F.data;
-  const u64 n = F.n;
-  const u32 down_is_fav = F.mode;  // decreasing mode: favourable = byte below its predecessor
-  const u32 runlen = F.sl - 1;
-  u32* __restrict__ eo = F.eo;
-  const u64 nblk = (n + kMarkBlock - 1) / kMarkBlock;
-  u64 blk = (span - F.mark_span0) * U;
-
-  u32 carry_byte = 0, carry_fav = 0;  // last byte / F bits of the 16 bytes before the block
-  if (blk > 0) {
-    u32 h[4];
-    load_halo(data, n, blk * kMarkBlock, h);
-    u32 up, dn;
-    compare16(h, 0u, up, dn);  // bit 0 is wrong (unknown predecessor) but is never used for SeqLength <= 16
-    carry_fav = down_is_fav ? dn : up;
-    carry_byte = h[3] >> 24;
-  }
-
-#pragma unroll 1
-  for (int u = 0; u < U; u++, blk++) {
-    if (blk >= nblk) break;
-    const u64 B = blk * kMarkBlock;
-    u32 x[4];
-    load_block(data, n, B, x);
-    const u32 last = x[3] >> 24;
-    const u32 prev = shift_up_lanes(last, carry_byte);
-    u32 up, dn;
-    compare16(x, prev, up, dn);
-    u32 fav = down_is_fav ? dn : up;
-    u32 opp = down_is_fav ? up : dn;
-    if (B == 0 && lane == 0) {  // byte 0 has no predecessor
-      fav &= ~1u;
-      opp &= ~1u;
-    }
-    const u32 fav_prev = shift_up_lanes(fav, carry_fav);
-    u32 e = run_ends16(fav, fav_prev, runlen);
-    const u64 q0 = B + 16ull * lane;
-    bool store = true;
-    if (B + kMarkBlock > n) {  // tail block: clear bits of bytes >= n
-      if (q0 >= n) {
-        e = opp = 0;
-        store = q0 < ((n + 63) & ~63ull);
-      } else if (n - q0 < 16) {
-        u32 keep = (1u << (u32)(n - q0)) - 1u;
-        e &= keep;
-        opp &= keep;
-      }
-    }
-    if (store) eo[(B >> 4) + lane] = e | (opp << 16);
-    const bool any_end = ballot(e != 0) != 0;  // run-end summary: one byte per 1 KiB block
-    if (lane == 0) F.esum[blk] = any_end ? 1 : 0;
-    carry_byte = readlane(last, 63);
-    carry_fav = readlane(fav, 63);
-  }
+  const FileDesc& F = files[file_of_span(files, nfiles, span)];
+  mark_span(F, span - F.mark_span0, span_blocks);
 }
 
-// ---------------------------------------------------------------------------
-// Launcher
-// ---------------------------------------------------------------------------
-
-hipError_t launch_mark(const FileDesc* d_files, u32 nfiles, u64 total_spans, u32 span_blocks, u32* d_counters,
-                       hipStream_t st) {
+hipError_t launch_mark(const FileDesc* d_files, u32 nfiles, u64 total_spans, u32 span_blocks, hipStream_t st) {
   const u64 groups = (total_spans + kWavesPerGroup - 1) / kWavesPerGroup;
-  dim3 grid((u32)(groups ? groups : 1)), block(256);
-  switch (span_blocks) {
-    case 4: hipLaunchKernelGGL(mark_kernel<4>, grid, block, 0, st, d_files, nfiles, total_spans, d_counters); break;
-    case 16: hipLaunchKernelGGL(mark_kernel<16>, grid, block, 0, st, d_files, nfiles, total_spans, d_counters); break;
-    default: hipLaunchKernelGGL(mark_kernel<8>, grid, block, 0, st, d_files, nfiles, total_spans, d_counters); break;
-  }
+  hipLaunchKernelGGL(mark_kernel, dim3((u32)(groups ? groups : 1)), dim3(256), 0, st, d_files, nfiles, total_spans,
+                     span_blocks);
   return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
 // SeqCDC resolve step on CDNA4 (gfx950): the exact sequential state machine
-// of the paper run over the mark bits.
+// of the paper run over the mark bits, fused with marking in one persistent
+// pipeline kernel.
 //
 // From a cut at c (Sec. III-B) scanning starts at s = c + min - SeqLength;
 // the chunk ends one byte past the first run end E at or after s+SeqLength-1
@@ -12,17 +13,21 @@
 // Parallelism: a stream is split into segments.  A chain starts at every
 // segment start as if a cut were there (pass A).  The state after a cut
 // depends only on the cut's position, so once two chains share a cut they
-// agree from then on.  Pass B continues each chain past its segment until
-// one of its cuts belongs to the chain that owns that position; the stitch
-// then keeps the exact pieces and the compaction writes them out.
+// agree from then on.  Pass B continues each chain past its segment until one
+// of its cuts belongs to the chain that owns that position; the stitch then
+// keeps the exact pieces and the compaction writes them out.  Every
+// dependency between workgroups is a kernel boundary: mark, pass A, pass B,
+// stitch and compaction are separate launches, and the only shared state
+// inside a launch is its atomic work counter.
 //
-// Each chain is one workgroup of two waves: a consumer wave runs the state
-// machine and a producer wave streams the mark bits of the next sub-windows
-// (4 KiB of input, 1 KiB of bits each) from HBM into an LDS ring ahead of it,
-// so the consumer never waits on HBM latency in steady state.  A per-1 KiB
-// summary of run ends lets a chain cross regions with no run end (zero runs,
-// most short periodic patterns) without reading their bits: with no run end
-// before the limit, the chunk ends at the limit whatever the opposing pairs do.
+// A chain is one wave, and the waves of a workgroup take chains
+// independently.  Its state is wave-uniform (scalar registers); the lanes
+// hold one sub-window of mark bits (4 KiB of input, one 64-byte group per
+// lane) with per-window prefix counts, so every scan step is a handful of lane
+// reads and scalar operations.  A per-1 KiB summary of run ends lets a chain
+// cross regions with no run end (zero runs, most short periodic patterns)
+// without reading their bits: with no run end before the limit, the chunk
+// ends at the limit whatever the opposing pairs do.
 
 #include <hip/hip_runtime.h>
 
@@ -31,15 +36,10 @@
 namespace seqcdc {
 
 constexpr u32 kSubBytes = 4096;  // input bytes per sub-window: 64 groups, one per lane
-constexpr u32 kRing = 32;        // sub-windows in a chain's LDS ring (128 KiB of input ahead)
-constexpr u32 kBatch = 8;        // producer loads in flight per round
 constexpr u64 kDone = ~0ull;
 
 __device__ __forceinline__ u64 min64(u64 a, u64 b) { return a < b ? a : b; }
 __device__ __forceinline__ u64 max64(u64 a, u64 b) { return a > b ? a : b; }
-__device__ __forceinline__ u64 readfirst64(u64 v) {
-  return (u64)__builtin_amdgcn_readfirstlane((u32)v) | ((u64)__builtin_amdgcn_readfirstlane((u32)(v >> 32)) << 32);
-}
 
 // Position of the k-th (1-based) set bit of a wave-uniform word w: lane b
 // counts the set bits of w below b (mbcnt); the lanes with fewer than k such
@@ -56,105 +56,12 @@ __device__ __forceinline__ void unpack_group(const uint4& v, u64& E, u64& O) {
 }
 
 // ---------------------------------------------------------------------------
-// Sources of mark bits for a chain
-// ---------------------------------------------------------------------------
-
-struct RingLds {
-  uint4 slot[kRing][64];
-  u64 tag[kRing];  // sub-window held by each slot (kDone = none)
-  u64 want;        // consumer: lowest sub-window still needed; kDone = chain finished
-  u64 item;        // work item handed from thread 0 to both waves
-};
-
-// Reads sub-windows straight from HBM (used for rare re-walks).
-struct DirectSource {
-  const uint4* eo;
-  u64 groups;
-  __device__ __forceinline__ uint4 fetch(u64 sub) {
-    const u64 g = sub * 64 + lane_id();
-    return g < groups ? eo[g] : make_uint4(0, 0, 0, 0);
-  }
-};
-
-// Reads sub-windows straight from HBM and keeps the next one in flight: a
-// chain moves forward about one sub-window per chunk, so the load of the
-// next sub-window overlaps the work on the current one.
-struct PrefetchSource {
-  const uint4* eo;
-  u64 groups;
-  u64 nxt_sub;
-  uint4 nxt;
-  __device__ __forceinline__ uint4 load(u64 sub) {
-    const u64 g = sub * 64 + lane_id();
-    return g < groups ? eo[g] : make_uint4(0, 0, 0, 0);
-  }
-  __device__ __forceinline__ uint4 fetch(u64 sub) {
-    uint4 v;
-    if (sub == nxt_sub) v = nxt;
-    else v = load(sub);
-    nxt_sub = sub + 1;
-    nxt = load(sub + 1);
-    return v;
-  }
-};
-
-// Reads sub-windows from the LDS ring filled by the producer wave.
-struct RingSource {
-  RingLds* r;
-  __device__ __forceinline__ uint4 fetch(u64 sub) {
-    // every lane stores the same value: no divergent branch around the chain's state
-    __hip_atomic_store(&r->want, sub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    const u32 slot = (u32)(sub % kRing);
-    for (;;) {
-      u64 t = __hip_atomic_load(&r->tag[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (readfirst64(t) == sub) break;
-      __builtin_amdgcn_s_sleep(1);
-    }
-    return r->slot[slot][lane_id()];
-  }
-};
-
-// Producer wave: keeps the sub-windows [want, want + kRing) of the file in the ring.
-__device__ void ring_producer(RingLds* r, const FileDesc& F) {
-  const u32 lane = lane_id();
-  const uint4* eo = (const uint4*)F.eo;
-  const u64 groups = (F.n + 63) >> 6;
-  const u64 subs = (F.n + kSubBytes - 1) / kSubBytes;
-  u64 next = 0;
-  for (;;) {
-    const u64 w = readfirst64(__hip_atomic_load(&r->want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-    if (w == kDone) return;
-    if (next < w) next = w;  // the consumer jumped ahead
-    const u64 end = min64(w + kRing, subs);
-    if (next >= end) {  // ring full: the consumer needs about one sub-window per chunk
-      __builtin_amdgcn_s_sleep(8);
-      continue;
-    }
-    const u32 cnt = (u32)min64(end - next, kBatch);
-    uint4 v[kBatch];
-#pragma unroll
-    for (u32 i = 0; i < kBatch; i++) {
-      const u64 g = (next + i) * 64 + lane;
-      v[i] = make_uint4(0, 0, 0, 0);
-      if (i < cnt && g < groups) v[i] = eo[g];
-    }
-#pragma unroll
-    for (u32 i = 0; i < kBatch; i++)
-      if (i < cnt) r->slot[(next + i) % kRing][lane] = v[i];
-    if (lane == 0)
-      for (u32 i = 0; i < cnt; i++)
-        __hip_atomic_store(&r->tag[(next + i) % kRing], next + i, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-    next += cnt;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // The chain
 // ---------------------------------------------------------------------------
 
-template <class Src>
 struct Chain {
-  Src src;
+  const uint4* eo;    // EO16 groups of the file
+  u64 groups;
   u64 n, nblocks;
   const uint8_t* esum;
   u64 min_size, max_size;
@@ -173,8 +80,9 @@ struct Chain {
   bool sum_hit, hot;
 };
 
-template <class Src>
-__device__ __forceinline__ void chain_init(Chain<Src>& ch, const FileDesc& F) {
+__device__ __forceinline__ void chain_init(Chain& ch, const FileDesc& F) {
+  ch.eo = (const uint4*)F.eo;
+  ch.groups = (F.n + 63) >> 6;
   ch.n = F.n;
   ch.nblocks = (F.n + 1023) >> 10;
   ch.esum = F.esum;
@@ -194,10 +102,11 @@ __device__ __forceinline__ void chain_init(Chain<Src>& ch, const FileDesc& F) {
   ch.hot = false;
 }
 
-template <class Src>
-__device__ __forceinline__ void ensure(Chain<Src>& ch, u64 sub) {
+// Loads sub-window `sub` and its per-window facts.
+__device__ __forceinline__ void ensure(Chain& ch, u64 sub) {
   if (ch.cur == sub) return;
-  const uint4 v = ch.src.fetch(sub);
+  const u64 g = sub * 64 + lane_id();
+  const uint4 v = g < ch.groups ? ch.eo[g] : make_uint4(0, 0, 0, 0);
   unpack_group(v, ch.E, ch.O);
   ch.cur = sub;
   // per-window facts every scan of this window reuses
@@ -211,13 +120,12 @@ __device__ __forceinline__ void ensure(Chain<Src>& ch, u64 sub) {
   }
 }
 
-// Extend the summary knowledge from block b by one load (1024 blocks, 1 MiB
-// of input): afterwards blocks [b, sum_to) are known to hold no run end.
-template <class Src>
-__device__ void summary_extend(Chain<Src>& ch, u64 b) {
+// Extend the summary knowledge from block b by one load (up to 1024 blocks,
+// 1 MiB of input): afterwards blocks [b, sum_to) are known to hold no run end.
+__device__ void summary_extend(Chain& ch, u64 b) {
   const u32 lane = lane_id();
   const u64 nb = ch.nblocks;
-  u64 to = nb;
+  u64 to = b;
   bool hit = true;
   if (b < nb) {
     const u64 a = b & ~15ull;
@@ -240,12 +148,11 @@ __device__ void summary_extend(Chain<Src>& ch, u64 b) {
     if (bal) {
       const u32 l = ctz64(bal);
       to = a + 16ull * l + (u32)__builtin_ctz(readlane(m, l));
-    } else if (a + 1024 < nb) {
-      to = a + 1024;
-      hit = false;
+      hit = true;
+    } else {
+      to = min64(a + 1024, nb);
+      hit = to >= nb;
     }
-  } else {
-    to = b;
   }
   if (!(ch.sum_from <= b && b <= ch.sum_to)) ch.sum_from = b;
   ch.sum_to = to;
@@ -255,16 +162,14 @@ __device__ void summary_extend(Chain<Src>& ch, u64 b) {
 
 // True if no block in [b, ceil(L/1024)) holds a run end, using and extending
 // the summary knowledge.  Cheap when the knowledge already covers b.
-template <class Src>
-__device__ __forceinline__ bool no_end_before(Chain<Src>& ch, u64 b, u64 L) {
+__device__ __forceinline__ bool no_end_before(Chain& ch, u64 b, u64 L) {
   if (!(ch.sum_from <= b && b <= ch.sum_to)) summary_extend(ch, b);
   while (!ch.sum_hit && (ch.sum_to << 10) < L) summary_extend(ch, ch.sum_to);
   return (ch.sum_to << 10) >= L;
 }
 
 // Opposing pairs of the window at positions < pos (0 <= pos <= 4096).
-template <class Src>
-__device__ __forceinline__ u32 opp_before(const Chain<Src>& ch, u32 pos) {
+__device__ __forceinline__ u32 opp_before(const Chain& ch, u32 pos) {
   if (pos >= kSubBytes) return ch.total;
   const u32 g = pos >> 6, b = pos & 63;
   const u32 prior = readlane(ch.excl, g);
@@ -277,8 +182,7 @@ __device__ __forceinline__ u32 opp_before(const Chain<Src>& ch, u32 pos) {
 // seen), 1 (run end first, at pos) or 2 (trigger first, at pos).  A pair is
 // never both favourable and opposing, so the two never coincide.  Scalar work
 // on the window's precomputed run-end mask and opposing-pair prefix counts.
-template <class Src>
-__device__ __forceinline__ u32 scan_sub(Chain<Src>& ch, u32 pr, u32 er, u32 lr, u32& need, u32& pos) {
+__device__ __forceinline__ u32 scan_sub(Chain& ch, u32 pr, u32 er, u32 lr, u32& need, u32& pos) {
   const u32 lw = lr < kSubBytes ? lr : kSubBytes;  // scan limit inside this window
   u32 qe = kSubBytes;                              // first admissible run end (kSubBytes = none)
   if (er < lw) {
@@ -315,8 +219,7 @@ __device__ __forceinline__ u32 scan_sub(Chain<Src>& ch, u32 pr, u32 er, u32 lr, 
 
 // The cut that follows a cut (or a speculative start) at c.  Wave-uniform.
 // Offsets inside the chunk are 32-bit, relative to c (max_size <= 1 GiB).
-template <class Src>
-__device__ u64 next_cut(Chain<Src>& ch, u64 c) {
+__device__ u64 next_cut(Chain& ch, u64 c) {
   if (c >= ch.n) return ch.n;  // callers never ask past the end; keeps every loop progressing
   const u64 rem = ch.n - c;
   const u32 lim = rem > ch.max_size ? (u32)ch.max_size : (u32)rem;  // Sec. IV limit
@@ -357,76 +260,41 @@ __device__ u64 next_cut(Chain<Src>& ch, u64 c) {
 }
 
 // ---------------------------------------------------------------------------
-// Pass A: chains from every segment start
+// Pass A and pass B
 // ---------------------------------------------------------------------------
 
-// Thread 0 takes the next work item and sets the first sub-window the chain
-// will read, so the producer starts streaming at once.
-template <class FirstSub>
-__device__ __forceinline__ bool take_item(RingLds& ring, u32* head, u32 nitems, u64& item, FirstSub first_sub) {
-  for (u32 i = threadIdx.x; i < kRing; i += blockDim.x) ring.tag[i] = kDone;
-  if (threadIdx.x == 0) {
-    const u64 it = atomicAdd(head, 1u);
-    ring.item = it;
-    ring.want = it < nitems ? first_sub((u32)it) : kDone;
-  }
-  __syncthreads();
-  item = readfirst64(ring.item);  // wave-uniform: everything derived from it stays scalar
-  return item < nitems;
-}
-
-__global__ __launch_bounds__(128) void chains_kernel(const FileDesc* __restrict__ files, ChainWs ws,
-                                                     const u32* __restrict__ order, u32 nitems) {
-  __shared__ RingLds ring;
+// Pass A of one chain: cuts from its segment start (taken as a cut) until the
+// first cut at or past the segment end.  A single-segment file writes its
+// output directly; otherwise the cuts, exit cut last, go to the chain's list.
+__device__ __forceinline__ void run_pass_a(const FileDesc* __restrict__ files, const ChainWs& ws, u32 chain) {
   const u32 lane = lane_id();
-  const bool consumer = __builtin_amdgcn_readfirstlane(threadIdx.x) < 64;  // wave-uniform role
-  for (;;) {
-    u64 it;
-    auto first_sub = [&](u32 i) -> u64 {
-      const u32 ch = order[i];
-      const FileDesc& G = files[ws.chain_file[ch]];
-      return ((u64)(ch - G.chain0) * G.seg + G.min_size - G.sl + 1) / kSubBytes;
-    };
-    if (!take_item(ring, &ws.counters[0], nitems, it, first_sub)) return;
-    const u32 chain = order[it];
-    const FileDesc& F = files[ws.chain_file[chain]];
-    const u32 k = chain - F.chain0;
-    const u64 S = (u64)k * F.seg;
-    const u64 Send = (k + 1 == F.nseg) ? F.n : S + F.seg;
-    if (consumer) {
-      if (F.n == 0) {
-        *F.out_count = 0;
-      } else {
-        Chain<RingSource> ch;
-        ch.src.r = &ring;
-        chain_init(ch, F);
-        const bool direct = F.nseg == 1;
-        u64* dst = direct ? F.out : ws.list + ws.list_off[chain];
-        const u64 cap = direct ? F.out_cap : ~0ull;
-        u64 cnt = 0, c = S, buf = 0;
-        do {
-          c = next_cut(ch, c);
-          if (lane == (u32)(cnt & 63)) buf = c;
-          cnt++;
-          if ((cnt & 63) == 0 || c >= Send) {  // flush the lanes filled since the last flush
-            const u64 i = ((cnt - 1) & ~63ull) + lane;
-            if (i < cnt && i < cap) dst[i] = buf;
-          }
-        } while (c < Send);
-        if (direct) *F.out_count = cnt;
-        else ws.list_cnt[chain] = (u32)cnt;
+  const FileDesc& F = files[ws.chain_file[chain]];
+  const u32 k = chain - F.chain0;
+  const u64 S = (u64)k * F.seg;
+  const u64 Send = (k + 1 == F.nseg) ? F.n : S + F.seg;
+  const bool direct = F.nseg == 1;
+  u64 cnt = 0;
+  if (F.n) {
+    Chain ch;
+    chain_init(ch, F);
+    u64* dst = direct ? F.out : ws.list + ws.list_off[chain];
+    const u64 cap = direct ? F.out_cap : ~0ull;
+    u64 c = S, buf = 0;
+    do {
+      c = next_cut(ch, c);
+      if (lane == (u32)(cnt & 63)) buf = c;
+      cnt++;
+      if ((cnt & 63) == 0 || c >= Send) {  // flush the lanes filled since the last flush
+        const u64 i = ((cnt - 1) & ~63ull) + lane;
+        if (i < cnt && i < cap) dst[i] = buf;
       }
-      __hip_atomic_store(&ring.want, kDone, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-    } else {
-      ring_producer(&ring, F);
-    }
-    __syncthreads();
+    } while (c < Send);
+  }
+  if (lane == 0) {
+    if (direct) *F.out_count = cnt;
+    else ws.list_cnt[chain] = (u32)cnt;
   }
 }
-
-// ---------------------------------------------------------------------------
-// Pass B: continuations
-// ---------------------------------------------------------------------------
 
 // Membership of x in the sorted main part (entries [0, cnt)) of a list,
 // streaming forward (x must not decrease between calls on one cursor).
@@ -459,75 +327,84 @@ __device__ __forceinline__ i32 cursor_find(ListCursor& lc, u64 x) {
   }
 }
 
-// Continue chain k from its exit cut until one of its cuts is also a cut of
-// the chain that owns that position (or that chain's segment start).
-__global__ __launch_bounds__(128) void continue_kernel(const FileDesc* __restrict__ files, ChainWs ws,
-                                                       const u32* __restrict__ order, u32 nitems) {
-  __shared__ RingLds ring;
-  const u32 lane = lane_id();
-  const bool consumer = __builtin_amdgcn_readfirstlane(threadIdx.x) < 64;  // wave-uniform role
-  for (;;) {
-    u64 it;
-    auto first_sub = [&](u32 i) -> u64 {
-      const u32 ch = order[i];
-      const FileDesc& G = files[ws.chain_file[ch]];
-      const u64 exit_cut = ws.list[ws.list_off[ch] + ws.list_cnt[ch] - 1];
-      return (exit_cut + G.min_size - G.sl + 1) / kSubBytes;
+// Pass B of `chain` (not the last of its file): its cuts from its exit cut
+// on, until one is also a cut of the chain that owns that position (or that
+// chain's segment start).
+__device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ files, const ChainWs& ws, u32 chain) {
+  const FileDesc& F = files[ws.chain_file[chain]];
+  const u64 n = F.n;
+  const u32 nseg = F.nseg;
+  u64 x = ws.list[ws.list_off[chain] + ws.list_cnt[chain] - 1];  // the exit cut
+  u32 conv_chain = nseg;
+  i32 conv_idx = -1;
+  u32 cc = 0;
+  u64* cont = ws.cont + ws.cont_off[chain];
+  if (x < n) {
+    u32 m = (u32)min64(x / F.seg, nseg - 1);
+    Chain ch;
+    chain_init(ch, F);
+    ListCursor lc;
+    auto open = [&](u32 seg) {
+      const u32 cm = F.chain0 + seg;
+      lc.list = ws.list + ws.list_off[cm];
+      lc.cnt = ws.list_cnt[cm] - 1;  // main part: all but the exit cut
+      lc.base = 0;
+      lc.loaded = false;
     };
-    if (!take_item(ring, &ws.counters[1], nitems, it, first_sub)) return;
-    const u32 chain = order[it];
-    const FileDesc& F = files[ws.chain_file[chain]];
-    const u64 n = F.n;
-    const u32 nseg = F.nseg;
-    u64 x = ws.list[ws.list_off[chain] + ws.list_cnt[chain] - 1];  // chain's exit cut
-    if (consumer) {
-      u32 conv_chain = nseg;
-      i32 conv_idx = -1;
-      u32 cc = 0;
-      u64* cont = ws.cont + ws.cont_off[chain];
-      if (x < n) {
-        Chain<RingSource> ch;
-        ch.src.r = &ring;
-        chain_init(ch, F);
-        u32 m = (u32)min64(x / F.seg, nseg - 1);
-        ListCursor lc;
-        auto open = [&](u32 seg) {
-          const u32 cm = F.chain0 + seg;
-          lc.list = ws.list + ws.list_off[cm];
-          lc.cnt = ws.list_cnt[cm] - 1;  // main part: all but the exit cut
-          lc.base = 0;
-          lc.loaded = false;
-        };
-        open(m);
-        for (;;) {
-          const u64 Sm = (u64)m * F.seg;
-          const i32 idx = (x == Sm) ? -1 : cursor_find(lc, x);
-          if (x == Sm || idx >= 0) {
-            conv_chain = m;
-            conv_idx = idx;
-            break;
-          }
-          if (cc < ws.cont_cap) cont[cc] = x;  // uniform condition; every lane stores the same value
-          cc++;
-          x = next_cut(ch, x);
-          if (x >= n) break;  // reached the end of the stream: conv_chain = nseg
-          const u32 m2 = (u32)min64(x / F.seg, nseg - 1);
-          if (m2 != m) {
-            m = m2;
-            open(m);
-          }
-        }
+    open(m);
+    for (;;) {
+      const u64 Sm = (u64)m * F.seg;
+      const i32 idx = (x == Sm) ? -1 : cursor_find(lc, x);
+      if (x == Sm || idx >= 0) {
+        conv_chain = m;
+        conv_idx = idx;
+        break;
       }
-      ws.conv_val[chain] = x;
-      ws.conv_chain[chain] = conv_chain;
-      ws.conv_idx[chain] = conv_idx;
-      ws.cont_cnt[chain] = cc;
-      __hip_atomic_store(&ring.want, kDone, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-    } else {
-      ring_producer(&ring, F);
+      if (cc < ws.cont_cap) cont[cc] = x;  // uniform condition; every lane stores the same value
+      cc++;
+      x = next_cut(ch, x);
+      if (x >= n) break;  // reached the end of the stream: conv_chain = nseg
+      const u32 m2 = (u32)min64(x / F.seg, nseg - 1);
+      if (m2 != m) {
+        m = m2;
+        open(m);
+      }
     }
-    __syncthreads();
   }
+  if (lane_id() == 0) {
+    ws.conv_val[chain] = x;
+    ws.conv_chain[chain] = conv_chain;
+    ws.conv_idx[chain] = conv_idx;
+    ws.cont_cnt[chain] = cc;
+  }
+}
+
+// Pass A over the chains in `order` (largest segments first), one wave per
+// chain; waves take chains from an atomic counter, independently of the other
+// waves of their workgroup.
+__global__ __launch_bounds__(256) void chains_kernel(const FileDesc* __restrict__ files, ChainWs ws,
+                                                     const u32* __restrict__ order, u32 nitems, u32* head) {
+  for (;;) {
+    const u32 t = wave_pop(head);
+    if (t >= nitems) return;
+    run_pass_a(files, ws, order[t]);
+  }
+}
+
+// Pass B over the chains in `order` (every chain but the last of each
+// multi-segment file).
+__global__ __launch_bounds__(256) void continue_kernel(const FileDesc* __restrict__ files, ChainWs ws,
+                                                       const u32* __restrict__ order, u32 nitems, u32* head) {
+  for (;;) {
+    const u32 t = wave_pop(head);
+    if (t >= nitems) return;
+    run_continuation(files, ws, order[t]);
+  }
+}
+
+// Clears the work counters.
+__global__ __launch_bounds__(64) void clear_kernel(u32* p, u32 count) {
+  if (threadIdx.x < count) p[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -641,7 +518,7 @@ __global__ __launch_bounds__(256) void stitch_kernel(const FileDesc* __restrict_
 __global__ __launch_bounds__(256) void compact_kernel(const FileDesc* __restrict__ files, ChainWs ws,
                                                       const u32* __restrict__ chains, u32 nchains) {
   const u32 lane = lane_id();
-  const u32 w = blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
+  const u32 w = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6));  // wave-uniform
   if (w >= nchains) return;
   const u32 chain = chains[w];
   if (!ws.active[chain]) return;
@@ -673,9 +550,7 @@ __global__ __launch_bounds__(256) void compact_kernel(const FileDesc* __restrict
       o += (stored - i < 64) ? stored - i : 64;
     }
     if (cc > stored) {
-      Chain<DirectSource> ch;
-      ch.src.eo = (const uint4*)F.eo;
-      ch.src.groups = (F.n + 63) >> 6;
+      Chain ch;
       chain_init(ch, F);
       u64 x = cont[stored - 1];
       for (u32 i = stored; i < cc; i++) {
@@ -694,17 +569,22 @@ __global__ __launch_bounds__(256) void compact_kernel(const FileDesc* __restrict
 // Launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_chains(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32 groups,
-                         hipStream_t st) {
-  if (!nitems) return hipSuccess;
-  hipLaunchKernelGGL(chains_kernel, dim3(groups), dim3(128), 0, st, d_files, ws, d_order, nitems);
+hipError_t launch_clear(u32* p, u32 count, hipStream_t st) {
+  hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(64), 0, st, p, count);
   return hipGetLastError();
 }
 
-hipError_t launch_continue(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32 groups,
-                           hipStream_t st) {
+hipError_t launch_chains(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32* head,
+                         u32 groups, hipStream_t st) {
   if (!nitems) return hipSuccess;
-  hipLaunchKernelGGL(continue_kernel, dim3(groups), dim3(128), 0, st, d_files, ws, d_order, nitems);
+  hipLaunchKernelGGL(chains_kernel, dim3(groups), dim3(256), 0, st, d_files, ws, d_order, nitems, head);
+  return hipGetLastError();
+}
+
+hipError_t launch_continue(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32* head,
+                           u32 groups, hipStream_t st) {
+  if (!nitems) return hipSuccess;
+  hipLaunchKernelGGL(continue_kernel, dim3(groups), dim3(256), 0, st, d_files, ws, d_order, nitems, head);
   return hipGetLastError();
 }
 

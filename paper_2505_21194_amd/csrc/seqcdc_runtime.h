@@ -48,7 +48,7 @@ struct Plan {
   u32 cus = 256;
   std::string arch;
   std::mutex mu;
-  DevBuf eo, esum, list, cont, chains, tables, misc;
+  DevBuf eo, esum, list, cont, chains, tables, flags, misc;
   HostBuf staging, readback;
   hipEvent_t call_done = nullptr, upload_done = nullptr;
   bool pending = false, upload_pending = false;
@@ -56,6 +56,10 @@ struct Plan {
   u32 last_nchains = 0, last_multi = 0;
   u64 seg_override = 0;
   u32 span_override = 0, waves_override = 0;
+  // optional per-phase timing of the last call: events before the mark
+  // kernel and after the mark, pass A, pass B and stitch + compaction
+  bool timing = false, timed = false;
+  hipEvent_t tev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 
   u64 segment_for(u64 n, const seqcdc_params* p) const;
   u32 span_blocks_for(const seqcdc_params* p) const;
