@@ -1,24 +1,33 @@
 """Chunking throughput of SeqCDC on one MI355X.
 
-Workload (one step = one pass of the whole hot path over the batch):
-  plain:   one 1 GiB mixed backup-like stream (1 MiB blocks: 50% uniform, 30% Zipf(1.1) text over 64 printable
-           symbols, 20% zero / repeated-16-byte runs), Increasing mode, 8 KiB target average (Table I: SeqLength 5,
-           SkipTrigger 50, SkipSize 256; min 4 KiB, max 16 KiB).  Stream resident in HBM; a step is one
-           seqcdc_chunk call (mark, speculative chains, continuations, stitch, compaction, count read-back).
+Workload of a step (the whole hot path over one batch of synthetic input):
+  plain:   one 1 GiB backup-like mixed stream (1 MiB blocks: 50% uniform bytes, 30% Zipf(1.1) text over 64
+           printable symbols, 20% zero / repeated-16-byte runs), Increasing mode, 8 KiB target average (Table I:
+           SeqLength 5, SkipTrigger 50, SkipSize 256; min 4 KiB, max 16 KiB).  The stream is resident in HBM when
+           the timed region starts; a step is one seqcdc_chunk call (mark, pass A chains, pass B continuations,
+           stitch, compaction, count read-back).
+Reported beside it (not the headline value):
   batched: 4096 files, log-normal sizes (median 256 KiB, sigma 1.5, clamped 4 KiB..64 MiB), each a mixed stream
-           under its own seed, 16 KiB average (SeqLength 5, 50 / 512, min 8 KiB, max 32 KiB), one
-           seqcdc_chunk_batch call per step, compared with one seqcdc_chunk call per file.
-value = plain input bytes per second (GB/s = 1e9 B/s).  Roofline: the mark kernel, the dominant one.
+           under its own seed, 16 KiB average (SeqLength 5, 50 / 512, min 8 KiB, max 32 KiB): one
+           seqcdc_chunk_batch call per step, against one seqcdc_chunk call per file.
+  serving: Poisson arrivals of requests (log-normal sizes, median 1 MiB, sigma 1.5, clamped 1 KiB..256 MiB) that
+           are slices of a device-resident snapshot series, 8 and 32 KiB averages mixed; offered load at 10/40/80 %
+           of the server's saturated rate; p50/p99 latency and GB/s, against the plain per-request path.
+value = plain input bytes per second (GB/s = 1e9 B/s).
 """
 import argparse
+import ctypes
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
 
+HERE = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
+METRIC = "chunking GB/s on 1 MI355X (batched vs plain) + % HBM peak; p99 request latency"
 
 
 def parse():
@@ -28,9 +37,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size-mib", type=int, default=1024)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--traffic-json", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                                                           "mark_traffic.json"))
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="oracle work to time on the host")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only run a 1 GiB device copy and the mark kernel (for rocprofv3 --pmc runs)")
+    ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "mark_traffic.json"))
     return ap.parse_args()
 
 
@@ -38,11 +50,181 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def mark_roofline(seq, torch, stream, d, n, p, traffic_json):
+    """Mark kernel alone on the same stream, timed with HIP events on that stream."""
+    groups = (n + 63) // 64
+    eo = torch.empty(4 * groups, dtype=torch.int32, device=d.device)
+    for _ in range(3):
+        seq.seqcdc_mark(d.data_ptr(), n, p, eo.data_ptr(), stream=stream)
+    reps = 20
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:  # one event pair around each launch: the average launch duration
+        a.record(stream)
+        seq.seqcdc_mark(d.data_ptr(), n, p, eo.data_ptr(), stream=stream)
+        b.record(stream)
+    evs[-1][1].synchronize()
+    ms = sum(a.elapsed_time(b) for a, b in evs) / reps
+    # algorithmic bytes of one launch: read every input byte, write 2 bits per byte (EO16) and one summary
+    # byte per 1 KiB block
+    alg = n + 16 * groups + (n + 1023) // 1024
+    achieved = alg / (ms * 1e-3) / 1e9
+    traffic = None
+    try:
+        from paper_2505_21194_amd import profiling
+        t = json.load(open(traffic_json))
+        if t.get("source_sha256") == profiling.source_digest() and t.get("n") == n:
+            traffic = round(t["bytes_per_launch"])
+    except Exception:
+        traffic = None
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "mark_kernel",
+            "kernel_ms": round(ms, 4), "alg_bytes_per_launch": alg}
+
+
+def batched(seq, torch, stream, plan, steps, warmup, dev):
+    import synth
+    nfiles = 4096
+    sizes = synth.lognormal_sizes(nfiles, 256 * 1024, 1.5, 4096, 64 << 20, seed=4).astype(np.int64)
+    total = int(sizes.sum())
+    log("batched: %d files, %.2f GiB" % (nfiles, total / 2 ** 30))
+    buf = torch.empty(total, dtype=torch.uint8, device=dev)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    for f in range(nfiles):
+        buf[int(offs[f]):int(offs[f + 1])].copy_(torch.from_numpy(synth.mixed(int(sizes[f]), seed=100000 + f)))
+    pb = seq.seqcdc_params_for_avg(16384)
+    cut_offs = [0]
+    for s in sizes:
+        cut_offs.append(cut_offs[-1] + seq.seqcdc_max_cuts(int(s), pb))
+    bcuts = torch.empty(cut_offs[-1], dtype=torch.int64, device=dev)
+    bcounts = torch.empty(nfiles, dtype=torch.int64, device=dev)
+    files = [(buf.data_ptr() + int(offs[f]), int(sizes[f]), 0) for f in range(nfiles)]
+
+    def bstep():
+        seq.seqcdc_chunk_batch(files, [pb], bcuts.data_ptr(), cut_offs, bcounts.data_ptr(), stream=stream, plan=plan)
+
+    for _ in range(warmup):
+        bstep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bstep()
+    torch.cuda.synchronize()
+    bdt = (time.perf_counter() - t0) / steps
+    counts = bcounts.cpu().numpy()
+    # one plain launch per file, the same files and parameters
+    pcap = max(cut_offs[i + 1] - cut_offs[i] for i in range(nfiles))
+    for f in range(16):
+        seq.seqcdc_chunk(files[f][0], files[f][1], pb, bcuts.data_ptr(), pcap, stream=stream, plan=plan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in range(nfiles):
+        seq.seqcdc_chunk(files[f][0], files[f][1], pb, bcuts.data_ptr(), pcap, stream=stream, plan=plan)
+    torch.cuda.synchronize()
+    pdt = time.perf_counter() - t0
+    del buf, bcuts
+    return {"files": nfiles, "bytes": total, "cuts": int(counts.sum()), "ms_per_step": round(bdt * 1e3, 3),
+            "GBps": round(total / bdt / 1e9, 1), "frac_hbm_peak_input": round(total / bdt / 1e9 / HBM_PEAK_GBS, 4),
+            "per_file_launch_GBps": round(total / pdt / 1e9, 2), "speedup_vs_per_file": round(pdt / bdt, 2),
+            "params": "avg 16 KiB: SeqLength 5, SkipTrigger 50, SkipSize 512, min 8 KiB, max 32 KiB"}
+
+
+def serving(seq, torch, dev):
+    """Poisson request stream through the serving loop; returns latency percentiles per offered load."""
+    import synth
+    vers = synth.snapshot_series(256 << 20, 3, seed=11, nedits=200, maxlen=4096)
+    dvers = [torch.from_numpy(v).to(dev) for v in vers]
+    rng = np.random.default_rng(5)
+    params = [seq.seqcdc_params_for_avg(8192), seq.seqcdc_params_for_avg(32768)]
+    nreq = 400
+    sizes = synth.lognormal_sizes(nreq, 1 << 20, 1.5, 1024, 256 << 20, seed=12).astype(np.int64)
+    reqs = []
+    for i in range(nreq):
+        v = int(rng.integers(len(vers)))
+        n = int(min(sizes[i], vers[v].size))
+        off = int(rng.integers(vers[v].size - n + 1))
+        reqs.append((dvers[v].data_ptr() + off, n, i % 2))
+    total = sum(r[1] for r in reqs)
+    arr = (seq.seqcdc_params * 2)(*params)
+    cfg = seq.seqcdc_server_config(0, 4 << 30, 256, 4, 64, 2, arr)
+    h = ctypes.c_void_p()
+    if seq.lib.seqcdc_server_create(ctypes.byref(cfg), ctypes.byref(h)):
+        raise RuntimeError(seq.last_error())
+
+    def run(rate_gbs):
+        """Submit reqs at Poisson arrival times for an offered load (GB/s); None = all at once."""
+        tickets = [None] * nreq
+        if rate_gbs:
+            mean = total / nreq
+            gaps = rng.exponential(mean / (rate_gbs * 1e9), nreq)
+            arrivals = np.cumsum(gaps)
+        else:
+            arrivals = np.zeros(nreq)
+        t0 = time.perf_counter()
+        for i, (ptr, n, pi) in enumerate(reqs):
+            while time.perf_counter() - t0 < arrivals[i]:
+                pass
+            t = ctypes.c_uint64()
+            if seq.lib.seqcdc_server_submit(h, ctypes.c_void_p(ptr), n, pi, ctypes.byref(t)):
+                raise RuntimeError(seq.last_error())
+            tickets[i] = t.value
+        lat = []
+        for t in tickets:
+            res = seq.seqcdc_result()
+            if seq.lib.seqcdc_server_wait(h, t, 60000.0, ctypes.byref(res)):
+                raise RuntimeError(seq.last_error())
+            lat.append(res.latency_ms)
+            seq.lib.seqcdc_server_release(h, t)
+        dt = time.perf_counter() - t0
+        lat = np.array(lat)
+        return {"offered_GBps": round(rate_gbs, 2) if rate_gbs else None, "GBps": round(total / dt / 1e9, 2),
+                "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+
+    try:
+        run(None)  # warm-up
+        sat = run(None)
+        peak = sat["GBps"]
+        loads = [run(frac * peak) for frac in (0.1, 0.4, 0.8)]
+    finally:
+        seq.lib.seqcdc_server_destroy(h)
+    # plain per-request path: one seqcdc_chunk call per request, back to back
+    cap = max(seq.seqcdc_max_cuts(n, params[pi]) for _, n, pi in reqs)
+    cuts = torch.empty(cap, dtype=torch.int64, device=dev)
+    plan = seq.seqcdc_plan_create()
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ptr, n, pi in reqs:
+        t1 = time.perf_counter()
+        seq.seqcdc_chunk(ptr, n, params[pi], cuts.data_ptr(), cap, plan=plan)
+        lat.append((time.perf_counter() - t1) * 1e3)
+    dt = time.perf_counter() - t0
+    seq.seqcdc_plan_destroy(plan)
+    return {"requests": nreq, "bytes": total, "saturated": sat, "loads": loads,
+            "plain_per_request": {"GBps": round(total / dt / 1e9, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                                  "p99_ms": round(float(np.percentile(lat, 99)), 3)}}
+
+
+def cpu_baseline(host, p, seconds):
+    """The oracle, single-threaded, over whole passes of the same stream until `seconds` of work."""
+    import oracle
+    kw = dict(mode=p.mode, seq_length=p.seq_length, min_size=p.min_size, max_size=p.max_size,
+              skip_trigger=p.skip_trigger, skip_size=p.skip_size)
+    t0 = time.perf_counter()
+    cuts = oracle.chunk(host, **kw)
+    one = time.perf_counter() - t0
+    reps = max(1, int(seconds / max(one, 1e-3)) - 1)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.chunk(host, **kw)
+    dt = (time.perf_counter() - t0 + one) / (reps + 1)
+    return cuts, {"value": round(host.size / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+                  "sample": "the whole %d MiB stream, %d passes, one thread" % (host.size >> 20, reps + 1)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).",
-              file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2505_21194_amd as seq
@@ -55,6 +237,19 @@ def main():
     host = synth.mixed(n, seed=2)
     d = torch.from_numpy(host).to(dev)
     p = seq.seqcdc_params_for_avg(8192)
+
+    if args.traffic_probe:
+        dst = torch.empty_like(d)
+        for _ in range(5):
+            dst.copy_(d)  # plain 1 GiB device copy: the calibration kernel
+        groups = (n + 63) // 64
+        eo = torch.empty(4 * groups, dtype=torch.int32, device=dev)
+        for _ in range(5):
+            seq.seqcdc_mark(d.data_ptr(), n, p, eo.data_ptr(), stream=stream)
+        torch.cuda.synchronize()
+        log("traffic probe done")
+        return
+
     cap = seq.seqcdc_max_cuts(n, p)
     cuts = torch.empty(cap, dtype=torch.int64, device=dev)
     plan = seq.seqcdc_plan_create()
@@ -74,105 +269,39 @@ def main():
     value = n / dt / 1e9
     log("plain: %.3f ms/step, %.1f GB/s, %d cuts" % (dt * 1e3, value, count))
 
-    # ---- dominant kernel: mark, timed with HIP events on the stream it is launched on
-    groups = (n + 63) // 64
-    eo = torch.empty(4 * groups, dtype=torch.int32, device=dev)
-    reps = 20
-    for _ in range(3):
-        seq.seqcdc_mark(d.data_ptr(), n, p, eo.data_ptr(), stream=stream)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(reps):
-        seq.seqcdc_mark(d.data_ptr(), n, p, eo.data_ptr(), stream=stream)
-    ev1.record(stream)
-    ev1.synchronize()
-    mark_ms = ev0.elapsed_time(ev1) / reps
-    alg_bytes = n + 16 * groups  # read every input byte once, write 2 bits per byte
-    achieved = alg_bytes / (mark_ms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            traffic = json.load(open(args.traffic_json)).get("bytes_per_launch_scaled")
-        except Exception:
-            traffic = None
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "mark_kernel",
-                "kernel_ms": round(mark_ms, 4), "alg_bytes_per_launch": alg_bytes}
-    log("mark: %.3f ms, %.1f GB/s algorithmic" % (mark_ms, achieved))
+    # per-phase durations of one more call (HIP events between the launches, on the same stream)
+    seq.seqcdc_plan_set_timing(plan, True)
+    step()
+    ph = seq.seqcdc_plan_phase_ms(plan)
+    seq.seqcdc_plan_set_timing(plan, False)
+    phases = {"mark": round(ph[0], 4), "pass_a": round(ph[1], 4), "pass_b": round(ph[2], 4),
+              "stitch_compact": round(ph[3], 4)}
+    log("phases (ms): %s" % phases)
 
-    extra = {}
-    # ---- batched
+    roofline = mark_roofline(seq, torch, stream, d, n, p, args.traffic_json)
+    roofline["step_share"] = round(roofline["kernel_ms"] / (dt * 1e3), 4)
+    log("mark: %s" % roofline)
+
+    extra = {"phases_ms": phases}
     if not args.no_batch:
-        nfiles = 4096
-        sizes = synth.lognormal_sizes(nfiles, 256 * 1024, 1.5, 4096, 64 << 20, seed=4).astype(np.int64)
-        total = int(sizes.sum())
-        log("batched: %d files, %.2f GiB" % (nfiles, total / 2 ** 30))
-        buf = torch.empty(total, dtype=torch.uint8, device=dev)
-        offs = np.concatenate([[0], np.cumsum(sizes)])
-        chunk_host = None
-        for f in range(nfiles):
-            chunk_host = synth.mixed(int(sizes[f]), seed=100000 + f)
-            buf[int(offs[f]):int(offs[f + 1])].copy_(torch.from_numpy(chunk_host))
-        pb = seq.seqcdc_params_for_avg(16384)
-        cut_offs = [0]
-        for s in sizes:
-            cut_offs.append(cut_offs[-1] + seq.seqcdc_max_cuts(int(s), pb))
-        bcuts = torch.empty(cut_offs[-1], dtype=torch.int64, device=dev)
-        bcounts = torch.empty(nfiles, dtype=torch.int64, device=dev)
-        files = [(buf.data_ptr() + int(offs[f]), int(sizes[f]), 0) for f in range(nfiles)]
-
-        def bstep():
-            seq.seqcdc_chunk_batch(files, [pb], bcuts.data_ptr(), cut_offs, bcounts.data_ptr(), stream=stream,
-                                   plan=plan)
-
-        for _ in range(args.warmup):
-            bstep()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            bstep()
-        torch.cuda.synchronize()
-        bdt = (time.perf_counter() - t0) / args.steps
-        # one plain launch per file
-        pcap = max(cut_offs[i + 1] - cut_offs[i] for i in range(nfiles))
-        t0 = time.perf_counter()
-        for f in range(nfiles):
-            seq.seqcdc_chunk(files[f][0], files[f][1], pb, bcuts.data_ptr(), pcap, stream=stream, plan=plan)
-        torch.cuda.synchronize()
-        pdt = time.perf_counter() - t0
-        extra["batched"] = {"files": nfiles, "bytes": total, "ms_per_step": round(bdt * 1e3, 3),
-                            "GBps": round(total / bdt / 1e9, 1), "per_file_launch_GBps": round(total / pdt / 1e9, 2),
-                            "speedup_vs_per_file": round(pdt / bdt, 2)}
+        extra["batched"] = batched(seq, torch, stream, plan, args.steps, args.warmup, dev)
         log("batched: %s" % extra["batched"])
+    if not args.no_serve:
+        extra["serving"] = serving(seq, torch, dev)
+        log("serving: %s" % extra["serving"])
 
-    # ---- CPU baseline: the oracle on a bounded sample of the same stream
     cpu = None
     if not args.no_cpu:
-        import oracle
-        sample = host[: min(n, 512 << 20)]
-        t0 = time.perf_counter()
-        oc = oracle.chunk(sample, mode=p.mode, seq_length=p.seq_length, min_size=p.min_size, max_size=p.max_size,
-                          skip_trigger=p.skip_trigger, skip_size=p.skip_size)
-        cdt = time.perf_counter() - t0
-        reps_cpu = max(1, int(10.0 / max(cdt, 1e-3)))
-        t0 = time.perf_counter()
-        for _ in range(min(reps_cpu, 50)):
-            oracle.chunk(sample, mode=p.mode, seq_length=p.seq_length, min_size=p.min_size, max_size=p.max_size,
-                         skip_trigger=p.skip_trigger, skip_size=p.skip_size)
-        cdt = (time.perf_counter() - t0) / min(reps_cpu, 50)
-        cpu = {"value": round(sample.size / cdt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": "first %d MiB of the same stream, %d repetitions, single thread" % (
-                   sample.size >> 20, min(reps_cpu, 50))}
+        want, cpu = cpu_baseline(host, p, args.cpu_seconds)
         got = cuts[:count].cpu().numpy().astype(np.uint64)
-        want_prefix = oc[oc < sample.size - (64 << 10)]
-        extra["parity_prefix_ok"] = bool(np.array_equal(got[:want_prefix.size], want_prefix))
-        log("cpu oracle: %s" % cpu)
+        extra["parity_vs_oracle"] = bool(got.size == want.size and np.array_equal(got, want))
+        log("cpu oracle: %s, parity %s" % (cpu, extra["parity_vs_oracle"]))
 
-    out = {"metric": "chunking GB/s on 1 MI355X (plain 1 GiB stream; batched in 'batched')", "value": round(value, 2),
-           "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-           "config": {"workload": "plain 1 GiB mixed stream, Increasing, avg 8 KiB (Table I)", "bytes": n,
-                      "cuts": count, "parallelism": "single GPU"},
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+           "config": {"workload": "plain %d MiB mixed backup-like stream, Increasing, avg 8 KiB (Table I)"
+                                  % args.size_mib, "bytes": n, "cuts": count, "parallelism": "single GPU"},
            "roofline": roofline, "cpu_baseline": cpu}
     out.update(extra)
     print(json.dumps(out), flush=True)
