@@ -109,7 +109,8 @@ int seqcdc_autotune(seqcdc_plan* plan, const void* d_sample, uint64_t n, const s
                     void* stream);
 
 /* Chunk one device-resident stream (the plain path).
- * d_stream: n bytes.  d_cuts: room for `cap` uint64 cut offsets.  On return
+ * d_stream: n bytes, n < 256 GiB (SEQCDC_EINVAL otherwise; the same limit
+ * holds per file in seqcdc_chunk_batch and for seqcdc_mark).  d_cuts: room for `cap` uint64 cut offsets.  On return
  * *h_count is the number of cuts; if it exceeds cap the call returns
  * SEQCDC_ECAPACITY and only the first cap cuts were written.  Synchronous:
  * the cuts are in d_cuts when it returns.  plan may be NULL (a per-device

@@ -462,6 +462,7 @@ int chunk_plan(Plan* pl, const void* d_stream, u64 n, const seqcdc_params* p, u6
     return SEQCDC_OK;
   }
   if (!d_stream || (!d_cuts && cap)) return fail(SEQCDC_EINVAL, "NULL stream or cut buffer");
+  if (n >= kMaxStream) return fail(SEQCDC_EINVAL, "streams must be shorter than 256 GiB");
   std::lock_guard<std::mutex> g(pl->mu);
   if ((rc = pl->misc.reserve(4096))) return rc;
   if ((rc = pl->readback.reserve(64))) return rc;
@@ -489,6 +490,7 @@ int chunk_batch(Plan* pl, const seqcdc_file* files, u32 nfiles, const seqcdc_par
     const seqcdc_file& F = files[f];
     if (F.params_index >= nparams) return fail(SEQCDC_EINVAL, "file %u: params_index out of range", f);
     if (F.n && !F.d_data) return fail(SEQCDC_EINVAL, "file %u: NULL data", f);
+    if (F.n >= kMaxStream) return fail(SEQCDC_EINVAL, "file %u: streams must be shorter than 256 GiB", f);
     if (h_off[f + 1] < h_off[f]) return fail(SEQCDC_EINVAL, "cut offsets must not decrease");
     const seqcdc_params* p = &params[F.params_index];
     const u64 room = h_off[f + 1] - h_off[f];
@@ -631,6 +633,7 @@ int seqcdc_mark(const void* d_stream, uint64_t n, const seqcdc_params* p, uint32
   if (rc) return rc;
   if (n == 0) return SEQCDC_OK;
   if (!d_stream || !d_eo) return fail(SEQCDC_EINVAL, "NULL pointer");
+  if (n >= kMaxStream) return fail(SEQCDC_EINVAL, "streams must be shorter than 256 GiB");
   Plan* pl = default_plan(&rc);
   if (!pl) return rc;
   std::lock_guard<std::mutex> g(pl->mu);

@@ -9,6 +9,37 @@ namespace seqcdc {
 typedef unsigned short us2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// Global-memory view of a pointer.  Pointers read from descriptors are
+// generic, and generic accesses compile to FLAT instructions (64-bit VGPR
+// addresses, counted by both the vector-memory and LDS/scalar counters);
+// through this view they compile to global loads and stores.
+#ifndef SEQCDC_GLOBAL
+#define SEQCDC_GLOBAL __attribute__((address_space(1)))
+#endif
+template <class T>
+__device__ __forceinline__ SEQCDC_GLOBAL T* as_global(T* p) {
+  return (SEQCDC_GLOBAL T*)p;
+}
+
+// LDS view of a pointer into a __shared__ array.
+#ifndef SEQCDC_LOCAL
+#define SEQCDC_LOCAL __attribute__((address_space(3)))
+#endif
+
+// Waits until every vector-memory operation of the wave has completed,
+// including LDS DMA writes (global_load_lds), which the compiler does not
+// track; the memory clobber keeps LDS reads from moving above it.
+#ifndef SEQCDC_WAIT_VMEM
+#define SEQCDC_WAIT_VMEM() asm volatile("s_waitcnt vmcnt(0)" ::: "memory")
+#endif
+
+// 16-byte global load (HIP's uint4 class cannot be copied out of a
+// global-address-space reference, a plain vector type can).
+__device__ __forceinline__ uint4 load16(const void* p) {
+  const u32x4 v = *as_global((const u32x4*)p);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 __device__ __forceinline__ u32 lane_id() { return __lane_id(); }
 
 // lane l receives v of lane l-1; lane 0 receives `carry` (DPP wave_shr:1).

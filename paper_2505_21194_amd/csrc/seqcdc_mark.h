@@ -94,7 +94,7 @@ __device__ __forceinline__ void load_block(const uint8_t* data, u64 n, u64 B, u3
   const u64 end_chunk = (r + n + 15) >> 4;        // aligned chunks overlapping the stream
   uint4 lo = make_uint4(0, 0, 0, 0);
   if (first < end_chunk) {
-    u32x4 v = __builtin_nontemporal_load((const u32x4*)(base + first));
+    u32x4 v = __builtin_nontemporal_load(as_global((const u32x4*)(base + first)));
     lo = make_uint4(v.x, v.y, v.z, v.w);
   }
   if (r == 0) {
@@ -108,7 +108,7 @@ __device__ __forceinline__ void load_block(const uint8_t* data, u64 n, u64 B, u3
   hi.w = __shfl_down(lo.w, 1);
   if (lane == 63) {
     hi = make_uint4(0, 0, 0, 0);
-    if (first + 1 < end_chunk) hi = base[first + 1];
+    if (first + 1 < end_chunk) hi = load16(base + first + 1);
   }
   funnel16(lo, hi, r, x);
 }
@@ -119,12 +119,12 @@ __device__ __forceinline__ void load_halo(const uint8_t* data, u64 n, u64 B, u32
   const u32 r = (u32)(addr & 15);
   const uint4* base = (const uint4*)(addr - r);
   const u64 c0 = (B - 16) >> 4;
-  uint4 lo = base[c0];
+  uint4 lo = load16(base + c0);
   if (r == 0) {
     x[0] = lo.x; x[1] = lo.y; x[2] = lo.z; x[3] = lo.w;
     return;
   }
-  uint4 hi = base[c0 + 1];  // overlaps byte B-1 < n, so it overlaps the stream
+  uint4 hi = load16(base + c0 + 1);  // overlaps byte B-1 < n, so it overlaps the stream
   funnel16(lo, hi, r, x);
 }
 
@@ -140,7 +140,8 @@ __device__ __forceinline__ void mark_span(const FileDesc& F, u64 span, u32 span_
   const u64 n = F.n;
   const u32 down_is_fav = F.mode;  // decreasing mode: favourable = byte below its predecessor
   const u32 runlen = F.sl - 1;
-  u32* __restrict__ eo = F.eo;
+  SEQCDC_GLOBAL u32* __restrict__ eo = as_global(F.eo);
+  SEQCDC_GLOBAL uint8_t* __restrict__ esum = as_global(F.esum);
   const u64 nblk = (n + kMarkBlock - 1) / kMarkBlock;
   u64 blk = span * span_blocks;
   const u64 blk_end = blk + span_blocks < nblk ? blk + span_blocks : nblk;
@@ -192,7 +193,7 @@ __device__ __forceinline__ void mark_span(const FileDesc& F, u64 span, u32 span_
       }
       if (store) eo[(B >> 4) + lane] = e | (opp << 16);
       const bool any_end = ballot(e != 0) != 0;  // run-end summary: one byte per 1 KiB block
-      if (lane == 0) F.esum[blk + d] = any_end ? 1 : 0;
+      if (lane == 0) esum[blk + d] = any_end ? 1 : 0;
       carry_byte = readlane(last, 63);
       carry_fav = readlane(fav, 63);
     }

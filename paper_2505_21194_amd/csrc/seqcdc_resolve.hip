@@ -59,15 +59,19 @@ __device__ __forceinline__ void unpack_group(const uint4& v, u64& E, u64& O) {
 // The chain
 // ---------------------------------------------------------------------------
 
+// Wave-uniform state (scalar registers) plus one sub-window of bits in the
+// lanes.  Indices of 64-byte groups, 1 KiB blocks and 4 KiB sub-windows are
+// 32-bit (streams are shorter than 256 GiB) and chunk-relative offsets are
+// 32-bit (max_size <= 1 GiB), so the state fits the scalar register file.
 struct Chain {
   const uint4* eo;    // EO16 groups of the file
-  u64 groups;
-  u64 n, nblocks;
   const uint8_t* esum;
-  u64 min_size, max_size;
-  u32 sl, trig, skip;
-  bool skipping;
-  u64 cur;            // sub-window held in E/O (kDone = none)
+  u64 n;
+  u32 groups, nblocks;
+  u32 min_size, max_size, sl, trig, skip;
+  u32 cur;            // sub-window held in E/O (kNone = none)
+  u32 nxt_sub;        // sub-window whose DMA into its slot was issued ahead (kNone = none)
+  SEQCDC_LOCAL u32x4* win;  // this wave's two LDS window slots (2 x 64 groups)
   u64 E, O;           // lane l: group cur*64 + l
   u32 incl;           // lane l: opposing pairs in groups 0..l of the window (inclusive prefix)
   u32 excl;           // lane l: opposing pairs in groups 0..l-1 of the window
@@ -76,23 +80,28 @@ struct Chain {
   u64 emask;          // bit l: group l holds a run end
   // summary knowledge: blocks [sum_from, sum_to) hold no run end; sum_hit says
   // whether sum_to is a block with a run end (or the end) rather than a horizon
-  u64 sum_from, sum_to;
+  u32 sum_from, sum_to;
   bool sum_hit, hot;
 };
 
-__device__ __forceinline__ void chain_init(Chain& ch, const FileDesc& F) {
+constexpr u32 kNone = 0xFFFFFFFFu;
+
+__device__ __forceinline__ bool skipping(const Chain& ch) { return ch.trig != kNoSkip; }
+
+__device__ __forceinline__ void chain_init(Chain& ch, const FileDesc& F, SEQCDC_LOCAL u32x4* win) {
+  ch.win = win;
   ch.eo = (const uint4*)F.eo;
-  ch.groups = (F.n + 63) >> 6;
-  ch.n = F.n;
-  ch.nblocks = (F.n + 1023) >> 10;
   ch.esum = F.esum;
-  ch.min_size = F.min_size;
-  ch.max_size = F.max_size;
+  ch.n = F.n;
+  ch.groups = (u32)((F.n + 63) >> 6);
+  ch.nblocks = (u32)((F.n + 1023) >> 10);
+  ch.min_size = (u32)F.min_size;
+  ch.max_size = (u32)F.max_size;
   ch.sl = F.sl;
   ch.trig = F.trig;
   ch.skip = F.skip;
-  ch.skipping = F.trig != kNoSkip;
-  ch.cur = kDone;
+  ch.cur = kNone;
+  ch.nxt_sub = kNone;
   ch.E = ch.O = 0;
   ch.incl = ch.excl = ch.total = 0;
   ch.fe = 64;
@@ -102,17 +111,38 @@ __device__ __forceinline__ void chain_init(Chain& ch, const FileDesc& F) {
   ch.hot = false;
 }
 
-// Loads sub-window `sub` and its per-window facts.
-__device__ __forceinline__ void ensure(Chain& ch, u64 sub) {
+// Starts the DMA of sub-window `sub` into its LDS slot (sub & 1): lane l
+// copies group sub*64 + l.  Lanes past the end read the last group instead
+// (always in bounds); their data is discarded when the slot is read.
+__device__ __forceinline__ void dma_window(const Chain& ch, u32 sub) {
+  const u32 g = sub * 64u + lane_id();
+  const u32 gs = g < ch.groups ? g : ch.groups - 1;
+  __builtin_amdgcn_global_load_lds(as_global((const void*)(ch.eo + gs)), ch.win + (sub & 1) * 64, 16, 0, 0);
+}
+
+// Loads sub-window `sub` and its per-window facts.  A chain moves forward
+// about one sub-window per chunk, so right after reading a window the DMA of
+// the next one into the other LDS slot is started; it has usually landed by
+// the time the chain gets there.
+__device__ __forceinline__ void ensure(Chain& ch, u32 sub) {
   if (ch.cur == sub) return;
-  const u64 g = sub * 64 + lane_id();
-  const uint4 v = g < ch.groups ? ch.eo[g] : make_uint4(0, 0, 0, 0);
+  if (sub != ch.nxt_sub) dma_window(ch, sub);
+  SEQCDC_WAIT_VMEM();
+  const u32x4 w = ch.win[(sub & 1) * 64 + lane_id()];
+  const bool inside = sub * 64u + lane_id() < ch.groups;
+  const uint4 v = inside ? make_uint4(w.x, w.y, w.z, w.w) : make_uint4(0, 0, 0, 0);
+  if ((sub + 1) * 64u < ch.groups) {
+    dma_window(ch, sub + 1);
+    ch.nxt_sub = sub + 1;
+  } else {
+    ch.nxt_sub = kNone;
+  }
   unpack_group(v, ch.E, ch.O);
   ch.cur = sub;
   // per-window facts every scan of this window reuses
   ch.emask = ballot(ch.E != 0);
   ch.fe = ch.E ? ctz64(ch.E) : 64u;
-  if (ch.skipping) {
+  if (skipping(ch)) {
     const u32 cnt = (u32)__popcll(ch.O);
     ch.incl = wave_incl_scan(cnt);
     ch.excl = ch.incl - cnt;
@@ -122,17 +152,17 @@ __device__ __forceinline__ void ensure(Chain& ch, u64 sub) {
 
 // Extend the summary knowledge from block b by one load (up to 1024 blocks,
 // 1 MiB of input): afterwards blocks [b, sum_to) are known to hold no run end.
-__device__ void summary_extend(Chain& ch, u64 b) {
+__device__ void summary_extend(Chain& ch, u32 b) {
   const u32 lane = lane_id();
-  const u64 nb = ch.nblocks;
-  u64 to = b;
+  const u32 nb = ch.nblocks;
+  u32 to = b;
   bool hit = true;
   if (b < nb) {
-    const u64 a = b & ~15ull;
-    const u64 idx = a + 16ull * lane;
+    const u32 a = b & ~15u;
+    const u32 idx = a + 16u * lane;
     // branch-free (keeps the chain state wave-uniform): every lane reads a valid
     // 16-byte chunk of the padded summary; bytes outside [b, nb) are masked
-    const uint4 v = *(const uint4*)(ch.esum + (idx < nb ? idx : ((nb - 1) & ~15ull)));
+    const uint4 v = load16(ch.esum + (idx < nb ? idx : ((nb - 1) & ~15u)));
     const u32 d[4] = {v.x, v.y, v.z, v.w};
     u32 m = 0;
 #pragma unroll
@@ -140,17 +170,17 @@ __device__ void summary_extend(Chain& ch, u64 b) {
       const u32 t = d[k] & 0x01010101u;
       m |= ((t | (t >> 7) | (t >> 14) | (t >> 21)) & 0xFu) << (4 * k);
     }
-    const u32 lo_sh = idx < b ? (u32)(b - idx) : 0u;  // < 16, only in lane 0
+    const u32 lo_sh = idx < b ? b - idx : 0u;  // < 16, only in lane 0
     m &= 0xFFFFu << lo_sh;
-    const u64 room = idx < nb ? nb - idx : 0;
-    m = room < 16 ? (m & ((1u << (u32)room) - 1u)) : m;
+    const u32 room = idx < nb ? nb - idx : 0u;
+    m = room < 16 ? (m & ((1u << room) - 1u)) : m;
     const u64 bal = ballot(m != 0);
     if (bal) {
       const u32 l = ctz64(bal);
-      to = a + 16ull * l + (u32)__builtin_ctz(readlane(m, l));
+      to = a + 16u * l + (u32)__builtin_ctz(readlane(m, l));
       hit = true;
     } else {
-      to = min64(a + 1024, nb);
+      to = a + 1024 < nb ? a + 1024 : nb;
       hit = to >= nb;
     }
   }
@@ -162,10 +192,10 @@ __device__ void summary_extend(Chain& ch, u64 b) {
 
 // True if no block in [b, ceil(L/1024)) holds a run end, using and extending
 // the summary knowledge.  Cheap when the knowledge already covers b.
-__device__ __forceinline__ bool no_end_before(Chain& ch, u64 b, u64 L) {
+__device__ __forceinline__ bool no_end_before(Chain& ch, u32 b, u64 L) {
   if (!(ch.sum_from <= b && b <= ch.sum_to)) summary_extend(ch, b);
-  while (!ch.sum_hit && (ch.sum_to << 10) < L) summary_extend(ch, ch.sum_to);
-  return (ch.sum_to << 10) >= L;
+  while (!ch.sum_hit && ((u64)ch.sum_to << 10) < L) summary_extend(ch, ch.sum_to);
+  return ((u64)ch.sum_to << 10) >= L;
 }
 
 // Opposing pairs of the window at positions < pos (0 <= pos <= 4096).
@@ -176,45 +206,30 @@ __device__ __forceinline__ u32 opp_before(const Chain& ch, u32 pos) {
   return b ? prior + (u32)__popcll(readlane64(ch.O, g) & ((1ull << b) - 1ull)) : prior;
 }
 
-// One step over the current sub-window, in byte offsets relative to its
-// start: the first run end at or after er and the need-th opposing pair at or
-// after pr, both before lr.  Returns 0 (neither; `need` reduced by the pairs
-// seen), 1 (run end first, at pos) or 2 (trigger first, at pos).  A pair is
-// never both favourable and opposing, so the two never coincide.  Scalar work
-// on the window's precomputed run-end mask and opposing-pair prefix counts.
-__device__ __forceinline__ u32 scan_sub(Chain& ch, u32 pr, u32 er, u32 lr, u32& need, u32& pos) {
-  const u32 lw = lr < kSubBytes ? lr : kSubBytes;  // scan limit inside this window
-  u32 qe = kSubBytes;                              // first admissible run end (kSubBytes = none)
-  if (er < lw) {
-    const u32 ge = er >> 6;
-    const u64 w = readlane64(ch.E, ge) & (~0ull << (er & 63));
-    if (w) {
-      qe = ge * 64u + ctz64(w);
-    } else {
-      const u64 m = ge < 63 ? (ch.emask & (~0ull << (ge + 1))) : 0ull;
-      if (m) {
-        const u32 g2 = ctz64(m);
-        qe = g2 * 64u + readlane(ch.fe, g2);
-      }
-    }
-    if (qe >= lw) qe = kSubBytes;
-  }
-  if (ch.skipping) {
-    const u32 base = opp_before(ch, pr);
-    const u32 seen = opp_before(ch, qe < kSubBytes ? qe : lw) - base;
-    if (seen >= need) {  // the need-th opposing pair from pr triggers a skip first
-      const u32 target = base + need;
-      const u32 gt = ctz64(ballot(ch.incl >= target));
-      pos = gt * 64u + select_bit(readlane64(ch.O, gt), target - readlane(ch.excl, gt));
-      return 2;
-    }
-    need -= seen;
-  }
-  if (qe < kSubBytes) {
-    pos = qe;
-    return 1;
-  }
-  return 0;
+// First admissible run end of the current sub-window at or after er (a
+// byte offset in the window, possibly >= kSubBytes), or kSubBytes if none.
+// Branch-free: the word of group er/64 and the first run end of the next
+// group holding one are both read, and the right one is selected.
+__device__ __forceinline__ u32 first_end(const Chain& ch, u32 er) {
+  const u32 ge = er < kSubBytes ? er >> 6 : 63u;
+  const u64 word = er < kSubBytes ? readlane64(ch.E, ge) & (~0ull << (er & 63)) : 0ull;
+  const u64 later = (er < kSubBytes && ge < 63) ? ch.emask & (~0ull << (ge + 1)) : 0ull;
+  const u32 g2 = later ? ctz64(later) : 63u;
+  const u32 f2 = readlane(ch.fe, g2);
+  return word ? ge * 64u + ctz64(word) : (later ? g2 * 64u + f2 : kSubBytes);
+}
+
+// Position in the current sub-window of the need-th opposing pair at or after
+// pr, or kSubBytes if the window holds fewer (then *left = pairs it holds at
+// or after pr).  The trigger is in the first group whose inclusive count
+// reaches (pairs before pr) + need, at the right set bit of that group.
+__device__ __forceinline__ u32 nth_opposing(const Chain& ch, u32 pr, u32 need, u32& left) {
+  const u32 base = opp_before(ch, pr);
+  left = ch.total - base;
+  if (need > left) return kSubBytes;
+  const u32 target = base + need;
+  const u32 gt = ctz64(ballot(ch.incl >= target));
+  return gt * 64u + select_bit(readlane64(ch.O, gt), target - readlane(ch.excl, gt));
 }
 
 // The cut that follows a cut (or a speculative start) at c.  Wave-uniform.
@@ -222,40 +237,52 @@ __device__ __forceinline__ u32 scan_sub(Chain& ch, u32 pr, u32 er, u32 lr, u32& 
 __device__ u64 next_cut(Chain& ch, u64 c) {
   if (c >= ch.n) return ch.n;  // callers never ask past the end; keeps every loop progressing
   const u64 rem = ch.n - c;
-  const u32 lim = rem > ch.max_size ? (u32)ch.max_size : (u32)rem;  // Sec. IV limit
-  u32 s = (u32)ch.min_size - ch.sl;                                 // Sec. III-B scan start
+  const u32 lim = rem > ch.max_size ? ch.max_size : (u32)rem;  // Sec. IV limit
+  u32 s = ch.min_size - ch.sl;                                 // Sec. III-B scan start
   u32 p = s + 1;                                                    // next pair (p-1, p) to examine
-  u32 e_lo = s + ch.sl - 1;                                         // earliest admissible run end
   u32 need = ch.trig;                                               // opposing pairs still to the trigger
   const u32 c32 = (u32)c;
   for (;;) {
     if (p >= lim) return c + lim;
     if (ch.hot) {  // inside a stretch known to hold no run end: nothing to find before the limit?
-      const u64 b = (c + (e_lo > p ? e_lo : p)) >> 10;
+      const u32 e_lo = s + ch.sl - 1;
+      const u32 b = (u32)((c + (e_lo > p ? e_lo : p)) >> 10);
       if (ch.sum_from <= b && b <= ch.sum_to) {
         if (no_end_before(ch, b, c + lim)) return c + lim;
       } else {
         ch.hot = false;
       }
     }
-    const u64 sub = (c + p) / kSubBytes;
+    const u32 sub = (u32)((c + p) / kSubBytes);
     ensure(ch, sub);
-    const u32 w = (u32)(sub * kSubBytes) - c32;  // window start relative to c (mod 2^32)
-    u32 pos = 0;
-    const u32 kind = scan_sub(ch, p - w, (e_lo > p ? e_lo : p) - w, lim - w, need, pos);
-    if (kind == 1) return c + (u32)(pos + w) + 1;  // Sec. III-A: boundary just past the run
-    if (kind == 2) {                             // Sec. III-C: skip SkipSize bytes after the trigger byte
-      const u64 s64 = (u64)(u32)(pos + w) + 1 + ch.skip;  // trigger byte relative to c, then the skip
-      if (s64 >= lim) return c + lim;
-      s = (u32)s64;
-      p = s + 1;
-      e_lo = s + ch.sl - 1;
-      need = ch.trig;
-      continue;
+    const u32 w = sub * kSubBytes - c32;  // window start relative to c (mod 2^32)
+    const u32 lw = lim - w < kSubBytes ? lim - w : kSubBytes;  // scan limit inside this window
+    // events inside this window; a skip that lands in it continues here
+    for (;;) {
+      const u32 e_lo = s + ch.sl - 1;  // earliest admissible run end
+      const u32 qe = first_end(ch, (e_lo > p ? e_lo : p) - w);
+      u32 pt = kSubBytes, left = 0;
+      if (skipping(ch)) pt = nth_opposing(ch, p - w, need, left);
+      if (qe < pt) {
+        if (qe < lw) return c + (u32)(w + qe) + 1;  // Sec. III-A: boundary just past the run (w may wrap)
+        return c + lim;                      // nothing before the limit
+      }
+      if (pt < kSubBytes) {  // Sec. III-C: skip SkipSize bytes after the trigger byte
+        if (pt >= lw) return c + lim;
+        const u64 s64 = (u64)(w + pt) + 1 + ch.skip;  // relative to c
+        if (s64 >= lim) return c + lim;
+        s = (u32)s64;
+        p = s + 1;
+        need = ch.trig;
+        if (p - w < kSubBytes) continue;  // the scan resumes in this window
+        break;
+      }
+      need -= left;  // no event in this window
+      p = w + kSubBytes;
+      if (p >= lim) return c + lim;
+      if (no_end_before(ch, (u32)((c + p) >> 10), c + lim)) return c + lim;  // no run end before the limit
+      break;
     }
-    p = w + kSubBytes;
-    if (p >= lim) return c + lim;
-    if (no_end_before(ch, (c + p) >> 10, c + lim)) return c + lim;  // no run end before the limit
   }
 }
 
@@ -266,7 +293,8 @@ __device__ u64 next_cut(Chain& ch, u64 c) {
 // Pass A of one chain: cuts from its segment start (taken as a cut) until the
 // first cut at or past the segment end.  A single-segment file writes its
 // output directly; otherwise the cuts, exit cut last, go to the chain's list.
-__device__ __forceinline__ void run_pass_a(const FileDesc* __restrict__ files, const ChainWs& ws, u32 chain) {
+__device__ __forceinline__ void run_pass_a(const FileDesc* __restrict__ files, const ChainWs& ws, u32 chain,
+                                           SEQCDC_LOCAL u32x4* win) {
   const u32 lane = lane_id();
   const FileDesc& F = files[ws.chain_file[chain]];
   const u32 k = chain - F.chain0;
@@ -276,8 +304,8 @@ __device__ __forceinline__ void run_pass_a(const FileDesc* __restrict__ files, c
   u64 cnt = 0;
   if (F.n) {
     Chain ch;
-    chain_init(ch, F);
-    u64* dst = direct ? F.out : ws.list + ws.list_off[chain];
+    chain_init(ch, F, win);
+    SEQCDC_GLOBAL u64* dst = as_global(direct ? F.out : ws.list + ws.list_off[chain]);
     const u64 cap = direct ? F.out_cap : ~0ull;
     u64 c = S, buf = 0;
     do {
@@ -310,7 +338,7 @@ __device__ __forceinline__ i32 cursor_find(ListCursor& lc, u64 x) {
   for (;;) {
     if (!lc.loaded) {
       const u32 i = lc.base + lane_id();
-      lc.vals = i < lc.cnt ? lc.list[i] : ~0ull;
+      lc.vals = i < lc.cnt ? as_global(lc.list)[i] : ~0ull;
       lc.loaded = true;
     }
     const u64 ge = ballot(lc.vals >= x);
@@ -330,7 +358,8 @@ __device__ __forceinline__ i32 cursor_find(ListCursor& lc, u64 x) {
 // Pass B of `chain` (not the last of its file): its cuts from its exit cut
 // on, until one is also a cut of the chain that owns that position (or that
 // chain's segment start).
-__device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ files, const ChainWs& ws, u32 chain) {
+__device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ files, const ChainWs& ws, u32 chain,
+                                                 SEQCDC_LOCAL u32x4* win) {
   const FileDesc& F = files[ws.chain_file[chain]];
   const u64 n = F.n;
   const u32 nseg = F.nseg;
@@ -338,11 +367,11 @@ __device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ fi
   u32 conv_chain = nseg;
   i32 conv_idx = -1;
   u32 cc = 0;
-  u64* cont = ws.cont + ws.cont_off[chain];
+  SEQCDC_GLOBAL u64* cont = as_global(ws.cont + ws.cont_off[chain]);
   if (x < n) {
     u32 m = (u32)min64(x / F.seg, nseg - 1);
     Chain ch;
-    chain_init(ch, F);
+    chain_init(ch, F, win);
     ListCursor lc;
     auto open = [&](u32 seg) {
       const u32 cm = F.chain0 + seg;
@@ -384,10 +413,12 @@ __device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ fi
 // waves of their workgroup.
 __global__ __launch_bounds__(256) void chains_kernel(const FileDesc* __restrict__ files, ChainWs ws,
                                                      const u32* __restrict__ order, u32 nitems, u32* head) {
+  __shared__ u32x4 win[kWavesPerGroup][2 * 64];
+  SEQCDC_LOCAL u32x4* mine = (SEQCDC_LOCAL u32x4*)win[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
   for (;;) {
     const u32 t = wave_pop(head);
     if (t >= nitems) return;
-    run_pass_a(files, ws, order[t]);
+    run_pass_a(files, ws, order[t], mine);
   }
 }
 
@@ -395,10 +426,12 @@ __global__ __launch_bounds__(256) void chains_kernel(const FileDesc* __restrict_
 // multi-segment file).
 __global__ __launch_bounds__(256) void continue_kernel(const FileDesc* __restrict__ files, ChainWs ws,
                                                        const u32* __restrict__ order, u32 nitems, u32* head) {
+  __shared__ u32x4 win[kWavesPerGroup][2 * 64];
+  SEQCDC_LOCAL u32x4* mine = (SEQCDC_LOCAL u32x4*)win[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
   for (;;) {
     const u32 t = wave_pop(head);
     if (t >= nitems) return;
-    run_continuation(files, ws, order[t]);
+    run_continuation(files, ws, order[t], mine);
   }
 }
 
@@ -518,6 +551,7 @@ __global__ __launch_bounds__(256) void stitch_kernel(const FileDesc* __restrict_
 __global__ __launch_bounds__(256) void compact_kernel(const FileDesc* __restrict__ files, ChainWs ws,
                                                       const u32* __restrict__ chains, u32 nchains) {
   const u32 lane = lane_id();
+  __shared__ u32x4 win[kWavesPerGroup][2 * 64];
   const u32 w = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6));  // wave-uniform
   if (w >= nchains) return;
   const u32 chain = chains[w];
@@ -551,7 +585,7 @@ __global__ __launch_bounds__(256) void compact_kernel(const FileDesc* __restrict
     }
     if (cc > stored) {
       Chain ch;
-      chain_init(ch, F);
+      chain_init(ch, F, (SEQCDC_LOCAL u32x4*)win[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
       u64 x = cont[stored - 1];
       for (u32 i = stored; i < cc; i++) {
         x = next_cut(ch, x);

@@ -11,6 +11,7 @@
 namespace seqcdc {
 
 constexpr u64 kMaxSegments = 65536;  // per stream
+constexpr u64 kMaxStream = 1ull << 38;  // 256 GiB: group and sub-window indices stay 32-bit
 
 struct DevBuf {
   void* p = nullptr;
