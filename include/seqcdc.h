@@ -91,18 +91,39 @@ int seqcdc_plan_set_tuning(seqcdc_plan* plan, uint64_t segment_bytes, uint32_t m
 int seqcdc_plan_get_tuning(seqcdc_plan* plan, uint64_t n, const seqcdc_params* p, uint64_t* segment_bytes,
                            uint32_t* mark_span_blocks, uint32_t* waves_per_cu);
 
+/* How a plan runs the resolve stage.  0 (the default): marking, pass A
+ * (chains) and pass B (continuations) are separate launches.  1: one
+ * persistent pipeline kernel hands out the marking of spans and the chains of
+ * every segment from one ordered list, so chains start while later parts of
+ * the input are still being marked and each chain continues past its segment
+ * as soon as the next chain's cut list exists; every published span costs an
+ * L2 write-back on its XCD, which makes this mode slower on MI355X at the
+ * sizes measured so far.  Both give the same cuts. */
+int seqcdc_plan_set_mode(seqcdc_plan* plan, int mode);
+
+/* Diagnostics of the plan's last pipeline-mode call (waits for it): out3[0] =
+ * continuations the pipeline kernel left to the resume kernel (they reached
+ * work not handed out yet), out3[1] = bounded waits that ran out (expected
+ * 0), out3[2] = 1 if a chain could not finish (expected 0; the call then
+ * reports an error).  All 0 after a phased-mode call. */
+int seqcdc_plan_stats(seqcdc_plan* plan, uint64_t* out3);
+
 /* Per-phase timing of the plan's calls (off by default; on adds HIP events
  * to every call).  seqcdc_plan_phase_ms waits for the plan's last timed call
- * and writes 4 durations in milliseconds: the mark kernel (with the clearing
- * of two work counters before it), pass A (speculative chains), pass B
- * (continuations) and stitch + compaction (the last two are 0 when no stream
- * had more than one segment).  SEQCDC_EINVAL if no timed call was made. */
+ * and writes 4 durations in milliseconds.  Mode 0: the mark kernel (with the
+ * clearing of the work counters before it), pass A (speculative chains),
+ * pass B (continuations), stitch + compaction.  Mode 1: the pipeline kernel
+ * (with the clearing before it), 0, the resume kernel (continuations the
+ * pipeline left), stitch + compaction.  The values after the first are 0 when
+ * no stream had more than one segment.  SEQCDC_EINVAL if no timed call was
+ * made. */
 int seqcdc_plan_set_timing(seqcdc_plan* plan, int on);
 int seqcdc_plan_phase_ms(seqcdc_plan* plan, float* ms4);
 
-/* Autotuner: time candidate segment sizes, mark spans and resolve occupancies
- * on the given device-resident sample stream, keep the fastest in the plan and
- * in a process-wide cache keyed by (arch, CU count, seq_length, average class).
+/* Autotuner: time candidate segment sizes, mark spans, resolve occupancies and
+ * the two resolve modes on the given device-resident sample stream, and keep
+ * the fastest in a process-wide cache keyed by (arch, CU count, seq_length,
+ * average class), which plans consult for settings not set explicitly.
  * Results are exact for every choice; only speed differs.  *best_ms receives
  * the best time (may be NULL). */
 int seqcdc_autotune(seqcdc_plan* plan, const void* d_sample, uint64_t n, const seqcdc_params* p, double* best_ms,

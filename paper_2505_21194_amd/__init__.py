@@ -66,6 +66,8 @@ _SIGS = {
     "seqcdc_plan_create": ([ctypes.c_int, ctypes.POINTER(_p)], ctypes.c_int),
     "seqcdc_plan_destroy": ([_p], ctypes.c_int),
     "seqcdc_plan_set_tuning": ([_p, _u64, _u32, _u32], ctypes.c_int),
+    "seqcdc_plan_set_mode": ([_p, ctypes.c_int], ctypes.c_int),
+    "seqcdc_plan_stats": ([_p, ctypes.POINTER(_u64)], ctypes.c_int),
     "seqcdc_plan_set_timing": ([_p, ctypes.c_int], ctypes.c_int),
     "seqcdc_plan_phase_ms": ([_p, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "seqcdc_plan_get_tuning": ([_p, _u64, ctypes.POINTER(seqcdc_params), ctypes.POINTER(_u64),
@@ -158,6 +160,18 @@ def seqcdc_plan_destroy(plan):
 
 def seqcdc_plan_set_tuning(plan, segment_bytes=0, mark_span_blocks=0, waves_per_cu=0):
     _check(lib.seqcdc_plan_set_tuning(plan, segment_bytes, mark_span_blocks, waves_per_cu))
+
+
+def seqcdc_plan_set_mode(plan, mode):
+    """0: mark, pass A and pass B as separate launches (default); 1: the fused pipeline kernel."""
+    _check(lib.seqcdc_plan_set_mode(plan, mode))
+
+
+def seqcdc_plan_stats(plan):
+    """(continuations resumed, bounded waits that ran out, stall flag) of the plan's last pipeline call."""
+    out = (_u64 * 3)()
+    _check(lib.seqcdc_plan_stats(plan, out))
+    return tuple(out)
 
 
 def seqcdc_plan_set_timing(plan, on=True):

@@ -1,5 +1,6 @@
 // Autotuner: picks the segment length of speculative resolution, the mark
-// span and the waves per CU of the persistent chain kernels by timing
+// span, the waves per CU of the persistent chain kernels and the resolve mode
+// (phased launches or the fused pipeline) by timing
 // candidates on a device-resident sample.  Every candidate produces the same
 // cuts; only speed differs.  Results go to a process-wide cache keyed by
 // (arch, CU count, SeqLength, average class).
@@ -57,6 +58,8 @@ extern "C" int seqcdc_autotune(seqcdc_plan* plan, const void* d_sample, uint64_t
 
   const u64 saved_seg = pl->seg_override;
   const u32 saved_span = pl->span_override, saved_waves = pl->waves_override;
+  const int saved_mode = pl->mode;
+  pl->mode = 0;
   TuneEntry best;
   best.key = plan_key(pl, p);
   best.ms = 1e30;
@@ -72,6 +75,7 @@ extern "C" int seqcdc_autotune(seqcdc_plan* plan, const void* d_sample, uint64_t
       best.seg_mult = seg_mult;
       best.span_blocks = span;
       best.waves_per_cu = waves;
+      best.mode = pl->mode;
     }
     return SEQCDC_OK;
   };
@@ -89,6 +93,11 @@ extern "C" int seqcdc_autotune(seqcdc_plan* plan, const void* d_sample, uint64_t
     for (u32 w : {8u, 16u, 24u})
       if ((rc = trial(m, s, w))) break;
   }
+  if (!rc) {  // the fused pipeline at the best shape so far
+    pl->mode = 1;
+    rc = trial(best.seg_mult, best.span_blocks, best.waves_per_cu);
+  }
+  pl->mode = saved_mode;
   pl->seg_override = saved_seg;
   pl->span_override = saved_span;
   pl->waves_override = saved_waves;

@@ -41,6 +41,7 @@ struct TuneEntry {
   u64 seg_mult = 256;  // segment length = seg_mult * min_size
   u32 span_blocks = 8;
   u32 waves_per_cu = 8;
+  int mode = 0;
   double ms = 0;
 };
 
@@ -57,6 +58,8 @@ struct Plan {
   u32 last_nchains = 0, last_multi = 0;
   u64 seg_override = 0;
   u32 span_override = 0, waves_override = 0;
+  int mode = -1;  // 0: mark, pass A, pass B as separate launches; 1: fused pipeline kernel; -1: tuned (else 0)
+  u32* last_resume = nullptr;  // device resume counters of the last pipeline call
   // optional per-phase timing of the last call: events before the mark
   // kernel and after the mark, pass A, pass B and stitch + compaction
   bool timing = false, timed = false;
@@ -65,6 +68,7 @@ struct Plan {
   u64 segment_for(u64 n, const seqcdc_params* p) const;
   u32 span_blocks_for(const seqcdc_params* p) const;
   u32 waves_for(const seqcdc_params* p) const;
+  int mode_for(const seqcdc_params* p) const;
 };
 
 int fail(int code, const char* fmt, ...);

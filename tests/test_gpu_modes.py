@@ -1,0 +1,119 @@
+"""Resolve modes, the autotuner and the dedup ratio of a backup-snapshot series.
+
+* The fused pipeline mode (marking and chains in one persistent kernel) gives the same cuts as the oracle
+  and as the phased mode, on the plain and batched paths, and reports no stalled chain or timed-out wait.
+* Whatever the autotuner picks, the cuts do not change.
+* Config 3 at reduced size: a uniform base plus versions made by seeded edits, chunked on the GPU at
+  4/8/16/32/64 KiB averages; the cut lists equal the oracle's and the space savings of Eq. 1 computed by
+  the library equal the oracle's.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2505_21194_amd as seq
+    return torch, seq
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def P(mode=0, sl=5, mn=4096, mx=16384, trig=50, skip=256):
+    return dict(mode=mode, seq_length=sl, min_size=mn, max_size=mx, skip_trigger=trig, skip_size=skip)
+
+
+@pytest.mark.parametrize("seg_kib", [64, 1024])
+@pytest.mark.parametrize("gen", ["uniform", "mixed"])
+def test_fused_mode_plain(env, seg_kib, gen):
+    torch, seq = env
+    data = (synth.uniform if gen == "uniform" else synth.mixed)(24 << 20, seed=seg_kib)
+    want = oracle.chunk(data, **P())
+    d = torch.from_numpy(data).cuda()
+    outs = {}
+    for mode in (1, 0):
+        plan = seq.seqcdc_plan_create()
+        try:
+            seq.seqcdc_plan_set_tuning(plan, segment_bytes=seg_kib << 10)
+            seq.seqcdc_plan_set_mode(plan, mode)
+            _say("plain", gen, "seg", seg_kib, "KiB mode", mode)
+            outs[mode] = seq.chunk(d, P(), plan=plan).cpu().numpy().astype(np.uint64)
+            if mode == 1:
+                resumed, timeouts, stall = seq.seqcdc_plan_stats(plan)
+                assert timeouts == 0 and stall == 0
+        finally:
+            seq.seqcdc_plan_destroy(plan)
+    assert np.array_equal(outs[1], want)
+    assert np.array_equal(outs[0], want)
+
+
+def test_fused_mode_batch(env):
+    torch, seq = env
+    rng = np.random.default_rng(9)
+    sizes = [int(x) for x in rng.integers(0, 2 << 20, 60)] + [0, 1, 4097, 6 << 20]
+    params = [P(), P(mode=1, sl=6, mn=8192, mx=32768, skip=512)]
+    datas = [synth.mixed(s, seed=500 + i) for i, s in enumerate(sizes)]
+    pidx = [i % 2 for i in range(len(sizes))]
+    tens = [torch.from_numpy(x).cuda() if x.size else torch.zeros(0, dtype=torch.uint8, device="cuda") for x in datas]
+    plan = seq.seqcdc_plan_create()
+    try:
+        seq.seqcdc_plan_set_tuning(plan, segment_bytes=128 << 10)
+        seq.seqcdc_plan_set_mode(plan, 1)
+        _say("fused batch", len(sizes), "files")
+        outs = seq.chunk_batch(tens, params, params_index=pidx, plan=plan)
+        assert seq.seqcdc_plan_stats(plan)[1:] == (0, 0)
+    finally:
+        seq.seqcdc_plan_destroy(plan)
+    for i, (x, o) in enumerate(zip(datas, outs)):
+        assert np.array_equal(o.cpu().numpy().astype(np.uint64), oracle.chunk(x, **params[pidx[i]])), i
+
+
+def test_autotune_keeps_results(env):
+    torch, seq = env
+    data = synth.mixed(16 << 20, seed=31)
+    d = torch.from_numpy(data).cuda()
+    p = seq.seqcdc_params_for_avg(8192)
+    pd = dict(mode=p.mode, seq_length=p.seq_length, min_size=p.min_size, max_size=p.max_size,
+              skip_trigger=p.skip_trigger, skip_size=p.skip_size)
+    want = oracle.chunk(data, **pd)
+    plan = seq.seqcdc_plan_create()
+    try:
+        _say("autotune 16 MiB")
+        ms = seq.seqcdc_autotune(plan, d.data_ptr(), d.numel(), p)
+        assert ms > 0
+        seg, span, waves = seq.seqcdc_plan_get_tuning(plan, d.numel(), p)
+        assert seg > 0 and span in (4, 8, 16, 32, 64) and 0 < waves <= 32
+        got = seq.chunk(d, p, plan=plan).cpu().numpy().astype(np.uint64)
+        assert np.array_equal(got, want)
+    finally:
+        seq.seqcdc_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("avg_kib", [4, 8, 16, 32, 64])
+def test_snapshot_dedup_matches_oracle(env, avg_kib):
+    torch, seq = env
+    versions = synth.snapshot_series(16 << 20, 4, seed=21, nedits=200, maxlen=4096)
+    p = seq.seqcdc_params_for_avg(avg_kib << 10)
+    pd = dict(mode=p.mode, seq_length=p.seq_length, min_size=p.min_size, max_size=p.max_size,
+              skip_trigger=p.skip_trigger, skip_size=p.skip_size)
+    _say("snapshot dedup", avg_kib, "KiB,", len(versions), "versions")
+    tens = [torch.from_numpy(v).cuda() for v in versions]
+    outs = seq.chunk_batch(tens, [p])
+    gpu_cuts = [o.cpu().numpy().astype(np.uint64) for o in outs]
+    ora_cuts = [oracle.chunk(v, **pd) for v in versions]
+    for g, w in zip(gpu_cuts, ora_cuts):
+        assert np.array_equal(g, w)
+    got = seq.seqcdc_dedup_stats(versions, gpu_cuts)
+    want = oracle.dedup_stats(versions, ora_cuts)
+    assert got[0] == want[0] and got[1] == want[1]  # original and unique bytes, exactly
+    assert got[2] == pytest.approx(want[2], abs=1e-12) and got[3] == pytest.approx(want[3], rel=1e-12)
+    assert 0.0 < want[2] < 0.75  # some chunks repeat across the 4 versions; never more than 3 of 4 copies
