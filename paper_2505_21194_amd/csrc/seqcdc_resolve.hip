@@ -36,6 +36,7 @@
 namespace seqcdc {
 
 constexpr u32 kSubBytes = 4096;  // input bytes per sub-window: 64 groups, one per lane
+constexpr u32 kRing = 8;         // LDS slots per wave: sub-window w lives in slot w % kRing
 
 __device__ __forceinline__ u64 min64(u64 a, u64 b) { return a < b ? a : b; }
 __device__ __forceinline__ u64 max64(u64 a, u64 b) { return a > b ? a : b; }
@@ -69,8 +70,9 @@ struct Chain {
   u32 groups, nblocks;
   u32 min_size, max_size, sl, trig, skip;
   u32 cur;            // sub-window held in E/O (kNone = none)
-  u32 nxt_sub;        // sub-window whose DMA into its slot was issued ahead (kNone = none)
-  SEQCDC_LOCAL u32x4* win;  // this wave's two LDS window slots (2 x 64 groups)
+  u32 pf_base;        // bit i of pf_mask: the DMA of sub-window pf_base + i into its slot was issued
+  u32 pf_mask;
+  SEQCDC_LOCAL u32x4* win;  // this wave's kRing LDS window slots (kRing x 64 groups)
   u64 E, O;           // lane l: group cur*64 + l
   u32 incl;           // lane l: opposing pairs in groups 0..l of the window (inclusive prefix)
   u32 excl;           // lane l: opposing pairs in groups 0..l-1 of the window
@@ -105,7 +107,8 @@ __device__ __forceinline__ void chain_init(Chain& ch, const FileDesc& F, SEQCDC_
   ch.trig = F.trig;
   ch.skip = F.skip;
   ch.cur = kNone;
-  ch.nxt_sub = kNone;
+  ch.pf_base = 0;
+  ch.pf_mask = 0;
   ch.E = ch.O = 0;
   ch.incl = ch.excl = ch.total = 0;
   ch.fe = 64;
@@ -192,33 +195,50 @@ __device__ bool make_ready(Chain& ch, u32 need_blk) {
   return true;
 }
 
-// Starts the DMA of sub-window `sub` into its LDS slot (sub & 1): lane l
+// Starts the DMA of sub-window `sub` into its LDS slot (sub % kRing): lane l
 // copies group sub*64 + l.  Lanes past the end read the last group instead
 // (always in bounds); their data is discarded when the slot is read.
 __device__ __forceinline__ void dma_window(const Chain& ch, u32 sub) {
   const u32 g = sub * 64u + lane_id();
   const u32 gs = g < ch.groups ? g : ch.groups - 1;
-  __builtin_amdgcn_global_load_lds(as_global((const void*)(ch.eo + gs)), ch.win + (sub & 1) * 64, 16, 0, 0);
+  __builtin_amdgcn_global_load_lds(as_global((const void*)(ch.eo + gs)), ch.win + (sub & (kRing - 1)) * 64, 16, 0,
+                                   0);
 }
 
-// Loads sub-window `sub` and its per-window facts.  A chain moves forward
-// about one sub-window per chunk, so right after reading a window the DMA of
-// the next one into the other LDS slot is started; it has usually landed by
-// the time the chain gets there.
-__device__ __forceinline__ bool ensure(Chain& ch, u32 sub) {
+// Loads sub-window `sub` and its per-window facts.  On entry to a window the
+// DMAs of the windows the chain is likely to need next are started: the next
+// one (the scan continues) and the two from `hint` on, the sub-window where
+// the scan would restart if a cut were found right at the current position (a
+// cut is usually a few hundred bytes away, and the scan after it starts
+// min_size - SeqLength bytes later).  Windows are entered in increasing
+// order, so the slots of the kRing - 1 windows after `sub` never collide.
+__device__ __forceinline__ bool ensure(Chain& ch, u32 sub, u32 hint) {
   if (ch.cur == sub) return true;
   if ((sub + 1) * 4 > ch.ready_blk && ch.ready_blk < ch.nblocks && !make_ready(ch, (sub + 1) * 4)) return false;
-  if (sub != ch.nxt_sub) dma_window(ch, sub);
+  const u32 d = sub - ch.pf_base;
+  u32 mask = d < kRing ? ch.pf_mask >> d : 0u;
+  if (!(mask & 1u)) dma_window(ch, sub);
   SEQCDC_WAIT_VMEM();
-  const u32x4 w = ch.win[(sub & 1) * 64 + lane_id()];
+  const u32x4 w = ch.win[(sub & (kRing - 1)) * 64 + lane_id()];
   const bool inside = sub * 64u + lane_id() < ch.groups;
   const uint4 v = inside ? make_uint4(w.x, w.y, w.z, w.w) : make_uint4(0, 0, 0, 0);
-  if ((sub + 1) * 64u < ch.groups && ((sub + 2) * 4 <= ch.ready_blk || ch.ready_blk >= ch.nblocks)) {
-    dma_window(ch, sub + 1);  // only once its bits exist
-    ch.nxt_sub = sub + 1;
-  } else {
-    ch.nxt_sub = kNone;
+  mask |= 1u;  // sub itself sits in its slot now
+  // windows worth fetching ahead: sub+1, hint and hint+1, inside the stream and already marked
+  u32 want = 2u;
+  const u32 hi = hint - sub;  // hint >= sub
+  if (hi < kRing - 1) want |= 3u << hi;
+  const u32 nwin = (ch.groups + 63) >> 6;
+  const u32 top = ch.ready_blk >= ch.nblocks ? nwin : ch.ready_blk >> 2;  // windows [.., top) exist
+  const u32 room = top > sub ? top - sub : 0u;
+  if (room < kRing) want &= (1u << room) - 1u;
+  want &= ~mask;
+  mask |= want;
+  while (want) {
+    dma_window(ch, sub + (u32)__builtin_ctz(want));
+    want &= want - 1u;
   }
+  ch.pf_base = sub;
+  ch.pf_mask = mask;
   unpack_group(v, ch.E, ch.O);
   ch.cur = sub;
   // per-window facts every scan of this window reuses
@@ -346,7 +366,7 @@ __device__ u64 next_cut(Chain& ch, u64 c) {
       }
     }
     const u32 sub = (u32)((c + p) / kSubBytes);
-    if (!ensure(ch, sub)) return kStop;
+    if (!ensure(ch, sub, (u32)((c + p + ch.min_size - ch.sl) / kSubBytes))) return kStop;
     const u32 w = sub * kSubBytes - c32;  // window start relative to c (mod 2^32)
     const u32 lw = lim - w < kSubBytes ? lim - w : kSubBytes;  // scan limit inside this window
     // events inside this window; a skip that lands in it continues here
@@ -563,7 +583,7 @@ __device__ __forceinline__ u64 exit_cut(const ChainWs& ws, u32 chain) {
 // waves of their workgroup.
 __global__ __launch_bounds__(256) void chains_kernel(const FileDesc* __restrict__ files, ChainWs ws,
                                                      const u32* __restrict__ order, u32 nitems, u32* head) {
-  __shared__ u32x4 win[kWavesPerGroup][2 * 64];
+  __shared__ u32x4 win[kWavesPerGroup][kRing * 64];
   SEQCDC_LOCAL u32x4* mine = (SEQCDC_LOCAL u32x4*)win[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
   for (;;) {
     const u32 t = wave_pop(head);
@@ -576,7 +596,7 @@ __global__ __launch_bounds__(256) void chains_kernel(const FileDesc* __restrict_
 // multi-segment file).
 __global__ __launch_bounds__(256) void continue_kernel(const FileDesc* __restrict__ files, ChainWs ws,
                                                        const u32* __restrict__ order, u32 nitems, u32* head) {
-  __shared__ u32x4 win[kWavesPerGroup][2 * 64];
+  __shared__ u32x4 win[kWavesPerGroup][kRing * 64];
   SEQCDC_LOCAL u32x4* mine = (SEQCDC_LOCAL u32x4*)win[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
   for (;;) {
     const u32 t = wave_pop(head);
@@ -591,7 +611,7 @@ __global__ __launch_bounds__(256) void continue_kernel(const FileDesc* __restric
 // continuation).  Waves of a workgroup are independent (no barriers).
 __global__ __launch_bounds__(256) void pipe_kernel(const FileDesc* __restrict__ files, u32 nfiles, ChainWs ws,
                                                    PipeWs pw) {
-  __shared__ u32x4 win[kWavesPerGroup][2 * 64];
+  __shared__ u32x4 win[kWavesPerGroup][kRing * 64];
   SEQCDC_LOCAL u32x4* mine = (SEQCDC_LOCAL u32x4*)win[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
   for (;;) {
     const u32 t = wave_pop(pw.head);
@@ -613,7 +633,7 @@ __global__ __launch_bounds__(256) void pipe_kernel(const FileDesc* __restrict__ 
 // Finishes the continuations the pipeline kernel stopped; everything is
 // marked and published by now.
 __global__ __launch_bounds__(256) void resume_kernel(const FileDesc* __restrict__ files, ChainWs ws, u32* resume) {
-  __shared__ u32x4 win[kWavesPerGroup][2 * 64];
+  __shared__ u32x4 win[kWavesPerGroup][kRing * 64];
   SEQCDC_LOCAL u32x4* mine = (SEQCDC_LOCAL u32x4*)win[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
   for (;;) {
     const u32 t = wave_pop(&resume[kResumeHead]);
@@ -743,7 +763,7 @@ __global__ __launch_bounds__(256) void stitch_kernel(const FileDesc* __restrict_
 __global__ __launch_bounds__(256) void compact_kernel(const FileDesc* __restrict__ files, ChainWs ws,
                                                       const u32* __restrict__ chains, u32 nchains) {
   const u32 lane = lane_id();
-  __shared__ u32x4 win[kWavesPerGroup][2 * 64];
+  __shared__ u32x4 win[kWavesPerGroup][kRing * 64];
   const u32 w = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6));  // wave-uniform
   if (w >= nchains) return;
   const u32 chain = chains[w];
