@@ -84,7 +84,8 @@ int seqcdc_plan_destroy(seqcdc_plan* plan);
  * number of mark spans); mark_span_blocks: 1 KiB blocks per mark span, the
  * unit of marking work (4, 8, 16, 32 or 64); waves_per_cu: waves per compute
  * unit of the persistent chain kernels, one chain per wave (4..32, a
- * multiple of 4). */
+ * multiple of 4; default 16; each wave keeps 8 KiB of windows in LDS, so at
+ * most 20 are resident per compute unit). */
 int seqcdc_plan_set_tuning(seqcdc_plan* plan, uint64_t segment_bytes, uint32_t mark_span_blocks,
                            uint32_t waves_per_cu);
 /* Current choices for a stream of n bytes under p. */
@@ -101,6 +102,18 @@ int seqcdc_plan_get_tuning(seqcdc_plan* plan, uint64_t n, const seqcdc_params* p
  * sizes measured so far.  Both give the same cuts. */
 int seqcdc_plan_set_mode(seqcdc_plan* plan, int mode);
 
+/* Overlapped batches (mode 0 only): the files of a seqcdc_chunk_batch call
+ * are taken largest first and cut into `groups` groups of about equal bytes.
+ * The caller's stream marks one group after the other while two side streams
+ * of the plan (default priority) run the chains of each group as soon as its
+ * marks are done, the continuations of the first group (the largest files)
+ * as soon as its chains are done, then the remaining continuations, stitch
+ * and compaction; the caller's stream waits for them before the call's work
+ * counts as done.  0 = default (off: on MI355X the chains slow the mark
+ * kernel down about as much as the overlap gains), 1 = off, up to 8.  Results
+ * do not depend on it. */
+int seqcdc_plan_set_overlap(seqcdc_plan* plan, uint32_t groups);
+
 /* Diagnostics of the plan's last pipeline-mode call (waits for it): out3[0] =
  * continuations the pipeline kernel left to the resume kernel (they reached
  * work not handed out yet), out3[1] = bounded waits that ran out (expected
@@ -114,9 +127,11 @@ int seqcdc_plan_stats(seqcdc_plan* plan, uint64_t* out3);
  * clearing of the work counters before it), pass A (speculative chains),
  * pass B (continuations), stitch + compaction.  Mode 1: the pipeline kernel
  * (with the clearing before it), 0, the resume kernel (continuations the
- * pipeline left), stitch + compaction.  The values after the first are 0 when
- * no stream had more than one segment.  SEQCDC_EINVAL if no timed call was
- * made. */
+ * pipeline left), stitch + compaction.  Overlapped batches: the marking of
+ * all groups on the caller's stream, then what each later step added after
+ * the previous one ended (chains of the last group, the continuations, stitch
+ * + compaction).  The values after the first are 0 when no stream had more
+ * than one segment.  SEQCDC_EINVAL if no timed call was made. */
 int seqcdc_plan_set_timing(seqcdc_plan* plan, int on);
 int seqcdc_plan_phase_ms(seqcdc_plan* plan, float* ms4);
 

@@ -67,6 +67,7 @@ _SIGS = {
     "seqcdc_plan_destroy": ([_p], ctypes.c_int),
     "seqcdc_plan_set_tuning": ([_p, _u64, _u32, _u32], ctypes.c_int),
     "seqcdc_plan_set_mode": ([_p, ctypes.c_int], ctypes.c_int),
+    "seqcdc_plan_set_overlap": ([_p, _u32], ctypes.c_int),
     "seqcdc_plan_stats": ([_p, ctypes.POINTER(_u64)], ctypes.c_int),
     "seqcdc_plan_set_timing": ([_p, ctypes.c_int], ctypes.c_int),
     "seqcdc_plan_phase_ms": ([_p, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
@@ -165,6 +166,11 @@ def seqcdc_plan_set_tuning(plan, segment_bytes=0, mark_span_blocks=0, waves_per_
 def seqcdc_plan_set_mode(plan, mode):
     """0: mark, pass A and pass B as separate launches (default); 1: the fused pipeline kernel."""
     _check(lib.seqcdc_plan_set_mode(plan, mode))
+
+
+def seqcdc_plan_set_overlap(plan, groups):
+    """Overlapped batches: 0 = default, 1 = off, 2..8 file groups whose marking overlaps earlier groups' chains."""
+    _check(lib.seqcdc_plan_set_overlap(plan, groups))
 
 
 def seqcdc_plan_stats(plan):

@@ -18,9 +18,10 @@
 
 namespace seqcdc {
 
-hipError_t launch_mark(const FileDesc* d_files, u32 nfiles, u64 total_spans, u32 span_blocks, hipStream_t st);
+hipError_t launch_mark(const FileDesc* d_files, const u32* d_hint, u64 span_lo, u64 span_hi, u32 span_blocks,
+                       hipStream_t st);
 hipError_t launch_clear(u32* p, u64 count, hipStream_t st);
-hipError_t launch_pipe(const FileDesc* d_files, u32 nfiles, const ChainWs& ws, const PipeWs& pw, u32 groups,
+hipError_t launch_pipe(const FileDesc* d_files, const u32* d_hint, const ChainWs& ws, const PipeWs& pw, u32 groups,
                        hipStream_t st);
 hipError_t launch_resume(const FileDesc* d_files, const ChainWs& ws, u32* resume, u32 groups, hipStream_t st);
 hipError_t launch_chains(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32* head,
@@ -184,7 +185,15 @@ u32 Plan::waves_for(const seqcdc_params* p) const {
   if (waves_override) return waves_override;
   TuneEntry te;
   if (p && tune_lookup(plan_key(this, p), &te)) return te.waves_per_cu;
-  return 32;
+  return 16;
+}
+
+// Overlapped batches are off unless asked for: on MI355X the chains that run
+// beside the mark kernel slow it down about as much as they gain.
+u32 Plan::groups_for(u32 nfiles, u64 total) const {
+  (void)total;
+  if (overlap) return std::min<u32>(overlap, std::min<u32>(nfiles, kMaxGroups));
+  return 1;
 }
 
 int Plan::mode_for(const seqcdc_params* p) const {
@@ -216,6 +225,12 @@ void plan_free(Plan* pl) {
   pl->readback.release();
   for (hipEvent_t& e : pl->tev)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t& e : pl->ev_mark)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : {pl->ev_chain_first, pl->ev_chain_last, pl->ev_join})
+    if (e) (void)hipEventDestroy(e);
+  for (hipStream_t s : pl->side)
+    if (s) (void)hipStreamDestroy(s);
   if (pl->call_done) (void)hipEventDestroy(pl->call_done);
   if (pl->upload_done) (void)hipEventDestroy(pl->upload_done);
 }
@@ -254,6 +269,18 @@ static hipError_t timing_mark(Plan* pl, int i, hipStream_t st) {
   return hipEventRecord(pl->tev[i], st);
 }
 
+// Side streams (default priority) and events of overlapped batches, created
+// on first use.
+static int ensure_side(Plan* pl) {
+  for (hipStream_t& s : pl->side)
+    if (!s) HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  for (hipEvent_t& e : pl->ev_mark)
+    if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (hipEvent_t* e : {&pl->ev_chain_first, &pl->ev_chain_last, &pl->ev_join})
+    if (!*e) HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  return SEQCDC_OK;
+}
+
 // Prepare and enqueue the whole pipeline for `specs` on `st`.
 // mark_only: run the mark step only (eo destination = specs[0].out as u32*).
 int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark_only) {
@@ -263,6 +290,16 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   if (pl->pending && pl->last_stream != st) HIP_TRY(hipStreamWaitEvent(st, pl->call_done, 0));
 
   // ---- host-side layout
+  // Overlapped batches take the files largest first and cut them into groups
+  // of about equal bytes; everything below (spans, chains) is numbered in
+  // that order, so each group owns a contiguous range of spans and chains.
+  const bool fused = !mark_only && pl->mode_for(specs[0].p) == 1;
+  u64 total_n = 0;
+  for (u32 f = 0; f < nfiles; f++) total_n += specs[f].n;
+  u32 G = (mark_only || fused) ? 1 : pl->groups_for(nfiles, total_n);
+  std::vector<u32> perm(nfiles);
+  for (u32 f = 0; f < nfiles; f++) perm[f] = f;
+  if (G > 1) std::stable_sort(perm.begin(), perm.end(), [&](u32 a, u32 b) { return specs[a].n > specs[b].n; });
   std::vector<FileDesc> fd(nfiles);
   u64 eo_bytes = 0, esum_bytes = 0, spans = 0, list_entries = 0, cont_entries = 0;
   u32 nchains = 0, cont_cap = 64;
@@ -270,7 +307,7 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   const u32 waves = pl->waves_for(specs[0].p);
   std::vector<u32> multi;
   for (u32 f = 0; f < nfiles; f++) {
-    const Spec& s = specs[f];
+    const Spec& s = specs[perm[f]];
     FileDesc& d = fd[f];
     d.data = s.data;
     d.n = s.n;
@@ -326,14 +363,32 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
       }
     }
   }
+  // group g holds files [gfile[g], gfile[g+1]); empty groups are dropped
+  std::vector<u32> gfile{0};
+  if (G > 1) {
+    u64 acc = 0;
+    for (u32 f = 0; f < nfiles && gfile.size() < G; f++) {
+      acc += fd[f].n;
+      if (acc * G >= total_n * gfile.size() && f + 1 < nfiles) gfile.push_back(f + 1);
+    }
+  }
+  gfile.push_back(nfiles);
+  G = (u32)gfile.size() - 1;
+  auto chain_at = [&](u32 f) { return f < nfiles ? fd[f].chain0 : nchains; };
+  auto span_at = [&](u32 f) { return f < nfiles ? fd[f].mark_span0 : spans; };
   for (u32 c = 0; c < nchains; c++) order[c] = c;
-  if (nfiles > 1)
-    std::stable_sort(order.begin(), order.end(), [&](u32 a, u32 b) { return work[a] > work[b]; });
+  for (u32 g = 0; g < G; g++)  // pass A takes each group's chains largest segment first
+    if (gfile[g + 1] - gfile[g] > 1)
+      std::stable_sort(order.begin() + chain_at(gfile[g]), order.begin() + chain_at(gfile[g + 1]),
+                       [&](u32 a, u32 b) { return work[a] > work[b]; });
+  // continuations of the first group's boundaries come first in `border`
+  const u32 border_first =
+      (u32)(std::lower_bound(border.begin(), border.end(), chain_at(gfile.size() > 2 ? gfile[1] : nfiles)) -
+            border.begin());
 
   // fused pipeline: one ordered list of mark spans and chains, largest files
   // first; a chain comes after every span its pass A can read (bytes below its
   // segment end plus max_size)
-  const bool fused = !mark_only && pl->mode_for(specs[0].p) == 1;
   const u64 sb = (u64)U * kMarkBlock;
   std::vector<u32> items, span_pos, chain_pos;
   if (fused) {
@@ -378,13 +433,14 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
                                          nchains * 4ull, nchains * 4ull, nchains * 4ull, nchains * 4ull,
                                          nchains * 8ull, nchains * 4ull, nchains * 8ull});
   if ((rc = pl->chains.reserve(chain_bytes))) return rc;
+  const u64 nhint = spans / kHintSpans + 2;
   const size_t table_bytes =
       carve_size({nfiles * sizeof(FileDesc), nchains * 4ull, nchains * 8ull, nchains * 8ull, nchains * 4ull,
                   border.size() * 4 + 4, multi.size() * 4 + 4, compact.size() * 4 + 4, nitems * 4ull + 4,
-                  span_pos.size() * 4 + 4, chain_pos.size() * 4 + 4});
+                  span_pos.size() * 4 + 4, chain_pos.size() * 4 + 4, nhint * 4ull});
   if ((rc = pl->tables.reserve(table_bytes))) return rc;
   // work counters (each on its own cache line); fused: done flags and the resume list
-  const u64 nflags = fused ? 64 + spans + (u64)nchains + 64 + kResumeList + nchains : 64;
+  const u64 nflags = fused ? 64 + spans + (u64)nchains + 64 + kResumeList + nchains : 16ull * (G + 3);
   if ((rc = pl->flags.reserve(nflags * 4))) return rc;
 
   // assign device pointers
@@ -413,6 +469,7 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   u32* h_items = carve<u32>(cur, nitems + 1);
   u32* h_span_pos = carve<u32>(cur, span_pos.size() + 1);
   u32* h_chain_pos = carve<u32>(cur, chain_pos.size() + 1);
+  u32* h_hint = carve<u32>(cur, nhint);
   const size_t used = cur - h;
   memcpy(h_files, fd.data(), nfiles * sizeof(FileDesc));
   memcpy(h_chain_file, chain_file.data(), nchains * 4ull);
@@ -425,12 +482,19 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   if (nitems) memcpy(h_items, items.data(), nitems * 4ull);
   if (!span_pos.empty()) memcpy(h_span_pos, span_pos.data(), span_pos.size() * 4);
   if (!chain_pos.empty()) memcpy(h_chain_pos, chain_pos.data(), chain_pos.size() * 4);
+  // span hint: entry i = the file holding span 64 i (the last file past the end)
+  for (u32 i = 0; i < nhint; i++) h_hint[i] = nfiles - 1;
+  for (u32 f = 0; f < nfiles; f++) {
+    const u64 lo = fd[f].mark_span0, hi = f + 1 < nfiles ? fd[f + 1].mark_span0 : spans;
+    for (u64 i = (lo + kHintSpans - 1) / kHintSpans; i * kHintSpans < hi; i++) h_hint[i] = f;
+  }
   auto dev = [&](void* hp) { return (void*)(dbase + ((char*)hp - h)); };
   HIP_TRY(hipMemcpyAsync(dbase, h, used, hipMemcpyHostToDevice, st));
   HIP_TRY(hipEventRecord(pl->upload_done, st));
   pl->upload_pending = true;
 
   const FileDesc* d_files = (const FileDesc*)dev(h_files);
+  const u32* d_hint = (const u32*)dev(h_hint);
 
   // ---- chain workspace
   ChainWs ws;
@@ -457,7 +521,7 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   ws.stall = heads + 32;
   if (!fused) pl->last_resume = nullptr;
   if (mark_only) {
-    HIP_TRY(launch_mark(d_files, nfiles, spans, U, st));
+    HIP_TRY(launch_mark(d_files, d_hint, 0, spans, U, st));
   } else if (fused) {
     PipeWs pw;
     pw.items = (const u32*)dev(h_items);
@@ -474,7 +538,7 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
     const u32 groups = std::max<u32>(1, pl->cus * waves / kWavesPerGroup);  // 4 independent waves each
     HIP_TRY(timing_mark(pl, 0, st));
     HIP_TRY(launch_clear(heads, nflags, st));
-    HIP_TRY(launch_pipe(d_files, nfiles, ws, pw, groups, st));
+    HIP_TRY(launch_pipe(d_files, d_hint, ws, pw, groups, st));
     HIP_TRY(timing_mark(pl, 1, st));
     HIP_TRY(timing_mark(pl, 2, st));
     if (!multi.empty()) {
@@ -486,11 +550,11 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
       HIP_TRY(timing_mark(pl, 3, st));
     }
     HIP_TRY(timing_mark(pl, 4, st));
-  } else {
+  } else if (G == 1) {
     const u32 groups = std::max<u32>(1, pl->cus * waves / kWavesPerGroup);  // 4 independent waves each
     HIP_TRY(timing_mark(pl, 0, st));
     HIP_TRY(launch_clear(heads, 64, st));
-    HIP_TRY(launch_mark(d_files, nfiles, spans, U, st));
+    HIP_TRY(launch_mark(d_files, d_hint, 0, spans, U, st));
     HIP_TRY(timing_mark(pl, 1, st));
     HIP_TRY(launch_chains(d_files, ws, (const u32*)dev(h_order), nchains, heads,
                           std::min<u32>(groups, (nchains + 3) / 4), st));
@@ -506,6 +570,54 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
       HIP_TRY(timing_mark(pl, 3, st));
     }
     HIP_TRY(timing_mark(pl, 4, st));
+  } else {
+    // Overlapped: st marks the groups one after the other; side[0] runs the
+    // chains of group g once its marks are done; side[1] runs the
+    // continuations of the first group (the largest files, whose convergence
+    // tails are the longest) as soon as its chains are done, then those of
+    // the other groups, then stitch and compaction; st joins at the end.
+    // Counters: pass A of group g at heads[16 g], pass B at heads[16 G] and
+    // heads[16 (G+1)], the stall flag at heads[16 (G+2)].
+    if ((rc = ensure_side(pl))) return rc;
+    hipStream_t sa = pl->side[0], sb = pl->side[1];
+    ws.stall = heads + 16 * (G + 2);
+    const u32 groups = std::max<u32>(1, pl->cus * waves / kWavesPerGroup);
+    HIP_TRY(timing_mark(pl, 0, st));
+    HIP_TRY(launch_clear(heads, 16ull * (G + 3), st));
+    for (u32 g = 0; g < G; g++) {
+      HIP_TRY(launch_mark(d_files, d_hint, span_at(gfile[g]), span_at(gfile[g + 1]), U, st));
+      HIP_TRY(hipEventRecord(pl->ev_mark[g], st));
+    }
+    HIP_TRY(timing_mark(pl, 1, st));
+    const u32* d_order = (const u32*)dev(h_order);
+    for (u32 g = 0; g < G; g++) {
+      HIP_TRY(hipStreamWaitEvent(sa, pl->ev_mark[g], 0));
+      const u32 lo = chain_at(gfile[g]), cnt = chain_at(gfile[g + 1]) - lo;
+      HIP_TRY(launch_chains(d_files, ws, d_order + lo, cnt, heads + 16 * g,
+                            std::max<u32>(1, std::min<u32>(groups, (cnt + 3) / 4)), sa));
+      if (g == 0) HIP_TRY(hipEventRecord(pl->ev_chain_first, sa));
+    }
+    HIP_TRY(timing_mark(pl, 2, sa));
+    HIP_TRY(hipEventRecord(pl->ev_chain_last, sa));
+    if (!multi.empty()) {
+      const u32* d_border = (const u32*)dev(h_border);
+      const u32 nb = (u32)border.size();
+      HIP_TRY(hipStreamWaitEvent(sb, pl->ev_chain_first, 0));
+      HIP_TRY(launch_continue(d_files, ws, d_border, border_first, heads + 16 * G,
+                              std::max<u32>(1, std::min<u32>(groups, (border_first + 3) / 4)), sb));
+      HIP_TRY(hipStreamWaitEvent(sb, pl->ev_chain_last, 0));
+      HIP_TRY(launch_continue(d_files, ws, d_border + border_first, nb - border_first, heads + 16 * (G + 1),
+                              std::max<u32>(1, std::min<u32>(groups, (nb - border_first + 3) / 4)), sb));
+      HIP_TRY(timing_mark(pl, 3, sb));
+      HIP_TRY(launch_stitch(d_files, ws, (const u32*)dev(h_multi), (u32)multi.size(), sb));
+      HIP_TRY(launch_compact(d_files, ws, (const u32*)dev(h_compact), (u32)compact.size(), sb));
+    } else {
+      HIP_TRY(hipStreamWaitEvent(sb, pl->ev_chain_last, 0));
+      HIP_TRY(timing_mark(pl, 3, sb));
+    }
+    HIP_TRY(timing_mark(pl, 4, sb));
+    HIP_TRY(hipEventRecord(pl->ev_join, sb));
+    HIP_TRY(hipStreamWaitEvent(st, pl->ev_join, 0));
   }
   HIP_TRY(hipEventRecord(pl->call_done, st));
   pl->pending = true;
@@ -659,6 +771,15 @@ int seqcdc_plan_set_mode(seqcdc_plan* plan, int mode) {
   Plan* pl = (Plan*)plan;
   std::lock_guard<std::mutex> g(pl->mu);
   pl->mode = mode;
+  return SEQCDC_OK;
+}
+
+int seqcdc_plan_set_overlap(seqcdc_plan* plan, uint32_t groups) {
+  if (!plan) return fail(SEQCDC_EINVAL, "plan is NULL");
+  if (groups > kMaxGroups) return fail(SEQCDC_EINVAL, "groups must be 0..%u", kMaxGroups);
+  Plan* pl = (Plan*)plan;
+  std::lock_guard<std::mutex> g(pl->mu);
+  pl->overlap = groups;
   return SEQCDC_OK;
 }
 

@@ -81,16 +81,16 @@ extern "C" int seqcdc_autotune(seqcdc_plan* plan, const void* d_sample, uint64_t
   };
   // coordinate search: segment length, then mark span, then chain occupancy
   for (u64 m : {32ull, 64ull, 128ull, 256ull, 512ull, 1024ull})
-    if ((rc = trial(m, 16, 32))) break;
+    if ((rc = trial(m, 16, 16))) break;
   if (!rc) {
     const u64 m = best.seg_mult;
     for (u32 s : {8u, 32u, 64u})
-      if ((rc = trial(m, s, 32))) break;
+      if ((rc = trial(m, s, 16))) break;
   }
   if (!rc) {
     const u64 m = best.seg_mult;
     const u32 s = best.span_blocks;
-    for (u32 w : {8u, 16u, 24u})
+    for (u32 w : {8u, 12u, 20u})
       if ((rc = trial(m, s, w))) break;
   }
   if (!rc) {  // the fused pipeline at the best shape so far

@@ -13,6 +13,7 @@ constexpr u32 kNoSkip = 0xFFFFFFFFu;
 constexpr u32 kWaveSize = 64;
 constexpr u32 kMarkBlock = 1024;  // bytes per wave per mark step (64 lanes x 16 B)
 constexpr u32 kWavesPerGroup = 4;  // 256-thread workgroups
+constexpr u32 kHintSpans = 64;     // mark spans per entry of the span -> file hint table
 
 // One stream ("file") of a batch, as the kernels see it.
 //

@@ -81,35 +81,44 @@ __device__ __forceinline__ void funnel16(const uint4& lo, const uint4& hi, u32 r
   }
 }
 
-// Load the 16 bytes of this lane for the 1 KiB block at file offset B.  All
-// loads are 16-byte aligned: a 16-byte aligned chunk never straddles a page,
-// so chunks that overlap the stream [data, data+n) are safe to read whole;
-// bytes outside the stream are ignored by the caller.
-__device__ __forceinline__ void load_block(const uint8_t* data, u64 n, u64 B, u32 x[4]) {
+// The raw loads of this lane for the 1 KiB block at file offset B: the
+// aligned 16-byte chunk holding the lane's first byte and, for lane 63 of a
+// stream that does not start on a 16-byte boundary, the chunk after it (the
+// other lanes take theirs from their neighbour).  Both are issued before any
+// is used, so a batch of blocks keeps all its loads in flight.  All loads are
+// 16-byte aligned: such a chunk never straddles a page, so chunks that
+// overlap the stream [data, data+n) are safe to read whole; bytes outside
+// the stream are ignored by the caller.
+struct BlockLoad {
+  u32x4 lo, ext;
+};
+
+__device__ __forceinline__ void load_block(const uint8_t* data, u64 n, u64 B, BlockLoad& L) {
   const u32 lane = lane_id();
   const uintptr_t addr = (uintptr_t)data;
   const u32 r = (u32)(addr & 15);
-  const uint4* base = (const uint4*)(addr - r);  // aligned view; byte q of the stream is at r + q
+  const u32x4* base = (const u32x4*)(addr - r);  // aligned view; byte q of the stream is at r + q
   const u64 first = (B >> 4) + lane;              // aligned chunk index of this lane
   const u64 end_chunk = (r + n + 15) >> 4;        // aligned chunks overlapping the stream
-  uint4 lo = make_uint4(0, 0, 0, 0);
-  if (first < end_chunk) {
-    u32x4 v = __builtin_nontemporal_load(as_global((const u32x4*)(base + first)));
-    lo = make_uint4(v.x, v.y, v.z, v.w);
-  }
+  L.lo = u32x4{0, 0, 0, 0};
+  L.ext = u32x4{0, 0, 0, 0};
+  if (first < end_chunk) L.lo = __builtin_nontemporal_load(as_global(base + first));
+  if (r != 0 && lane == 63 && first + 1 < end_chunk) L.ext = __builtin_nontemporal_load(as_global(base + first + 1));
+}
+
+// The 16 stream bytes of this lane from its raw loads.
+__device__ __forceinline__ void block_bytes(const uint8_t* data, const BlockLoad& L, u32 x[4]) {
+  const u32 r = (u32)((uintptr_t)data & 15);
   if (r == 0) {
-    x[0] = lo.x; x[1] = lo.y; x[2] = lo.z; x[3] = lo.w;
+    x[0] = L.lo.x; x[1] = L.lo.y; x[2] = L.lo.z; x[3] = L.lo.w;
     return;
   }
-  uint4 hi;
+  uint4 lo = make_uint4(L.lo.x, L.lo.y, L.lo.z, L.lo.w), hi;
   hi.x = __shfl_down(lo.x, 1);
   hi.y = __shfl_down(lo.y, 1);
   hi.z = __shfl_down(lo.z, 1);
   hi.w = __shfl_down(lo.w, 1);
-  if (lane == 63) {
-    hi = make_uint4(0, 0, 0, 0);
-    if (first + 1 < end_chunk) hi = load16(base + first + 1);
-  }
+  if (lane_id() == 63) hi = make_uint4(L.ext.x, L.ext.y, L.ext.z, L.ext.w);
   funnel16(lo, hi, r, x);
 }
 
@@ -158,19 +167,21 @@ __device__ __forceinline__ void mark_span(const FileDesc& F, u64 span, u32 span_
 
 #pragma unroll 1
   for (; blk < blk_end; blk += kMarkBatch) {
-    u32 x[kMarkBatch][4];
+    BlockLoad ld[kMarkBatch];
 #pragma unroll
     for (u32 d = 0; d < kMarkBatch; d++) {
-      if (blk + d < blk_end) load_block(data, n, (blk + d) * kMarkBlock, x[d]);
+      if (blk + d < blk_end) load_block(data, n, (blk + d) * kMarkBlock, ld[d]);
     }
 #pragma unroll
     for (u32 d = 0; d < kMarkBatch; d++) {
       if (blk + d >= blk_end) break;
       const u64 B = (blk + d) * kMarkBlock;
-      const u32 last = x[d][3] >> 24;
+      u32 x[4];
+      block_bytes(data, ld[d], x);
+      const u32 last = x[3] >> 24;
       const u32 prev = shift_up_lanes(last, carry_byte);
       u32 up, dn;
-      compare16(x[d], prev, up, dn);
+      compare16(x, prev, up, dn);
       u32 fav = down_is_fav ? dn : up;
       u32 opp = down_is_fav ? up : dn;
       if (B == 0 && lane == 0) {  // byte 0 has no predecessor
@@ -201,8 +212,12 @@ __device__ __forceinline__ void mark_span(const FileDesc& F, u64 span, u32 span_
 }
 
 // File of a global mark span: the last file whose first span is <= span.
-__device__ __forceinline__ u32 file_of_span(const FileDesc* __restrict__ files, u32 nfiles, u64 span) {
-  u32 lo = 0, hi = nfiles;
+// hint[i] is the file holding span 64 i (entries past the last span: the last
+// file), so the search only covers the files that start among these 64 spans.
+__device__ __forceinline__ u32 file_of_span(const FileDesc* __restrict__ files, const u32* __restrict__ hint,
+                                            u64 span) {
+  const u64 h = span / kHintSpans;
+  u32 lo = hint[h], hi = hint[h + 1] + 1;
   while (hi - lo > 1) {
     u32 mid = (lo + hi) >> 1;
     if (files[mid].mark_span0 <= span) lo = mid;

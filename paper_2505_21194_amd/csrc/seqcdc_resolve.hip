@@ -609,8 +609,8 @@ __global__ __launch_bounds__(256) void continue_kernel(const FileDesc* __restric
 // The pipeline kernel: every wave takes items in list order until the list
 // is exhausted (marking a span, or a chain's pass A and then its
 // continuation).  Waves of a workgroup are independent (no barriers).
-__global__ __launch_bounds__(256) void pipe_kernel(const FileDesc* __restrict__ files, u32 nfiles, ChainWs ws,
-                                                   PipeWs pw) {
+__global__ __launch_bounds__(256) void pipe_kernel(const FileDesc* __restrict__ files, const u32* __restrict__ hint,
+                                                   ChainWs ws, PipeWs pw) {
   __shared__ u32x4 win[kWavesPerGroup][kRing * 64];
   SEQCDC_LOCAL u32x4* mine = (SEQCDC_LOCAL u32x4*)win[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
   for (;;) {
@@ -623,7 +623,7 @@ __global__ __launch_bounds__(256) void pipe_kernel(const FileDesc* __restrict__ 
       const FileDesc& F = files[ws.chain_file[chain]];
       if (chain + 1 < F.chain0 + F.nseg && x != kStop) run_continuation(files, ws, chain, mine, &pw, x, 0);
     } else {
-      const FileDesc& F = files[file_of_span(files, nfiles, code)];
+      const FileDesc& F = files[file_of_span(files, hint, code)];
       mark_span(F, code - F.mark_span0, pw.span_blocks);
       publish(&pw.span_done[code]);
     }
@@ -836,10 +836,10 @@ hipError_t launch_continue(const FileDesc* d_files, const ChainWs& ws, const u32
   return hipGetLastError();
 }
 
-hipError_t launch_pipe(const FileDesc* d_files, u32 nfiles, const ChainWs& ws, const PipeWs& pw, u32 groups,
+hipError_t launch_pipe(const FileDesc* d_files, const u32* d_hint, const ChainWs& ws, const PipeWs& pw, u32 groups,
                        hipStream_t st) {
   if (!pw.nitems) return hipSuccess;
-  hipLaunchKernelGGL(pipe_kernel, dim3(groups), dim3(256), 0, st, d_files, nfiles, ws, pw);
+  hipLaunchKernelGGL(pipe_kernel, dim3(groups), dim3(256), 0, st, d_files, d_hint, ws, pw);
   return hipGetLastError();
 }
 

@@ -11,6 +11,7 @@
 namespace seqcdc {
 
 constexpr u64 kMaxSegments = 65536;  // per stream
+constexpr u32 kMaxGroups = 8;        // file groups of an overlapped batch
 constexpr u64 kMaxStream = 1ull << 38;  // 256 GiB: group and sub-window indices stay 32-bit
 
 struct DevBuf {
@@ -64,11 +65,19 @@ struct Plan {
   // kernel and after the mark, pass A, pass B and stitch + compaction
   bool timing = false, timed = false;
   hipEvent_t tev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // overlapped batches: files in groups, largest first; the mark kernels of
+  // later groups run on the caller's stream while side[0] runs the chains of
+  // earlier ones and side[1] their continuations
+  u32 overlap = 0;  // groups (0: default, 1: off)
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t ev_mark[kMaxGroups] = {};
+  hipEvent_t ev_chain_first = nullptr, ev_chain_last = nullptr, ev_join = nullptr;
 
   u64 segment_for(u64 n, const seqcdc_params* p) const;
   u32 span_blocks_for(const seqcdc_params* p) const;
   u32 waves_for(const seqcdc_params* p) const;
   int mode_for(const seqcdc_params* p) const;
+  u32 groups_for(u32 nfiles, u64 total) const;
 };
 
 int fail(int code, const char* fmt, ...);

@@ -117,3 +117,53 @@ def test_snapshot_dedup_matches_oracle(env, avg_kib):
     assert got[0] == want[0] and got[1] == want[1]  # original and unique bytes, exactly
     assert got[2] == pytest.approx(want[2], abs=1e-12) and got[3] == pytest.approx(want[3], rel=1e-12)
     assert 0.0 < want[2] < 0.75  # some chunks repeat across the 4 versions; never more than 3 of 4 copies
+
+
+@pytest.mark.parametrize("groups", [1, 2, 4, 8])
+def test_overlapped_batch(env, groups):
+    """File groups marked on the caller's stream while side streams run earlier groups' chains: same cuts."""
+    torch, seq = env
+    rng = np.random.default_rng(40 + groups)
+    sizes = [int(x) for x in rng.integers(0, 3 << 20, 36)] + [0, 1, 70000, 8 << 20, 5 << 20]
+    params = [P(), P(mode=1, sl=6, mn=8192, mx=32768, skip=512)]
+    pidx = [i % 2 for i in range(len(sizes))]
+    datas = [synth.mixed(s, seed=900 + i) for i, s in enumerate(sizes)]
+    tens = [torch.from_numpy(x).cuda() if x.size else torch.zeros(0, dtype=torch.uint8, device="cuda") for x in datas]
+    plan = seq.seqcdc_plan_create()
+    try:
+        seq.seqcdc_plan_set_tuning(plan, segment_bytes=128 << 10)
+        seq.seqcdc_plan_set_overlap(plan, groups)
+        seq.seqcdc_plan_set_timing(plan, True)
+        for rep in range(2):  # the plan's buffers, streams and events are reused
+            _say("overlapped batch", groups, "groups, call", rep)
+            outs = seq.chunk_batch(tens, params, params_index=pidx, plan=plan)
+            for i, (x, o) in enumerate(zip(datas, outs)):
+                assert np.array_equal(o.cpu().numpy().astype(np.uint64), oracle.chunk(x, **params[pidx[i]])), (rep, i)
+        ms = seq.seqcdc_plan_phase_ms(plan)
+        assert len(ms) == 4 and all(m >= 0 for m in ms)
+    finally:
+        seq.seqcdc_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_many_small_files(env, mode):
+    """Thousands of tiny files, many per 64 mark spans (the span -> file lookup), plus a few large ones."""
+    torch, seq = env
+    rng = np.random.default_rng(77 + mode)
+    sizes = [int(x) for x in rng.integers(0, 12000, 2500)] + [0, 3 << 20, 0, 1, 1 << 20]
+    p = P()
+    datas = [synth.uniform(s, seed=3000 + i) for i, s in enumerate(sizes)]
+    host = np.concatenate([d for d in datas if d.size] + [np.zeros(1, np.uint8)])
+    buf = torch.from_numpy(host).cuda()
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    tens = [buf[int(offs[i]):int(offs[i + 1])] for i in range(len(sizes))]
+    plan = seq.seqcdc_plan_create()
+    try:
+        seq.seqcdc_plan_set_tuning(plan, segment_bytes=256 << 10, mark_span_blocks=4)
+        seq.seqcdc_plan_set_mode(plan, mode)
+        _say("many small files, mode", mode)
+        outs = seq.chunk_batch(tens, [p], plan=plan)
+    finally:
+        seq.seqcdc_plan_destroy(plan)
+    for i, (x, o) in enumerate(zip(datas, outs)):
+        assert np.array_equal(o.cpu().numpy().astype(np.uint64), oracle.chunk(x, **p)), i
