@@ -50,20 +50,11 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def mark_roofline(seq, torch, stream, d, n, p, traffic_json):
-    """Mark kernel alone on the same stream, timed with HIP events on that stream."""
+def mark_roofline(n, kernel_ms, traffic_json):
+    """Roofline of the mark kernel from its average duration inside the chunking calls (HIP events around its
+    launch on the call's stream) and, when they match the current sources, the PMC bytes per launch."""
     groups = (n + 63) // 64
-    eo = torch.empty(4 * groups, dtype=torch.int32, device=d.device)
-    for _ in range(3):
-        seq.seqcdc_mark(d.data_ptr(), n, p, eo.data_ptr(), stream=stream)
-    reps = 20
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(stream)  # back-to-back launches between one event pair: the average launch duration
-    for _ in range(reps):
-        seq.seqcdc_mark(d.data_ptr(), n, p, eo.data_ptr(), stream=stream)
-    b.record(stream)
-    b.synchronize()
-    ms = a.elapsed_time(b) / reps
+    ms = kernel_ms
     # algorithmic bytes of one launch: read every input byte, write 2 bits per byte (EO16) and one summary
     # byte per 1 KiB block
     alg = n + 16 * groups + (n + 1023) // 1024
@@ -113,6 +104,20 @@ def batched(seq, torch, stream, plan, steps, warmup, dev):
     torch.cuda.synchronize()
     bdt = (time.perf_counter() - t0) / steps
     counts = bcounts.cpu().numpy()
+    # the same batch prepared once and replayed as a hipGraph
+    gb = seq.seqcdc_batch_prepare(ftab, [pb], bcuts.data_ptr(), otab, bcounts.data_ptr(), settings=plan)
+    try:
+        for _ in range(warmup):
+            seq.seqcdc_batch_launch(gb, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            seq.seqcdc_batch_launch(gb, stream=stream)
+        torch.cuda.synchronize()
+        gdt = (time.perf_counter() - t0) / steps
+        graph_same = bool(np.array_equal(bcounts.cpu().numpy(), counts))
+    finally:
+        seq.seqcdc_batch_destroy(gb)
     # one plain launch per file, the same files and parameters
     pcap = max(cut_offs[i + 1] - cut_offs[i] for i in range(nfiles))
     for f in range(16):
@@ -126,6 +131,8 @@ def batched(seq, torch, stream, plan, steps, warmup, dev):
     del buf, bcuts
     return {"files": nfiles, "bytes": total, "cuts": int(counts.sum()), "ms_per_step": round(bdt * 1e3, 3),
             "GBps": round(total / bdt / 1e9, 1), "frac_hbm_peak_input": round(total / bdt / 1e9 / HBM_PEAK_GBS, 4),
+            "graph_ms_per_step": round(gdt * 1e3, 3), "graph_GBps": round(total / gdt / 1e9, 1),
+            "graph_counts_match": graph_same,
             "per_file_launch_GBps": round(total / pdt / 1e9, 2), "speedup_vs_per_file": round(pdt / bdt, 2),
             "params": "avg 16 KiB: SeqLength 5, SkipTrigger 50, SkipSize 512, min 8 KiB, max 32 KiB"}
 
@@ -271,16 +278,20 @@ def main():
     value = n / dt / 1e9
     log("plain: %.3f ms/step, %.1f GB/s, %d cuts" % (dt * 1e3, value, count))
 
-    # per-phase durations of one more call (HIP events between the launches, on the same stream)
+    # per-phase durations of as many more calls: HIP events recorded by the library on the call's stream between
+    # its launches (the mark phase is the mark kernel alone, with events right before and after its launch)
     seq.seqcdc_plan_set_timing(plan, True)
-    step()
-    ph = seq.seqcdc_plan_phase_ms(plan)
+    acc = np.zeros(4)
+    for _ in range(args.steps):
+        step()
+        acc += np.array(seq.seqcdc_plan_phase_ms(plan))
     seq.seqcdc_plan_set_timing(plan, False)
+    ph = acc / args.steps
     phases = {"mark": round(ph[0], 4), "pass_a": round(ph[1], 4), "pass_b": round(ph[2], 4),
               "stitch_compact": round(ph[3], 4)}
     log("phases (ms): %s" % phases)
 
-    roofline = mark_roofline(seq, torch, stream, d, n, p, args.traffic_json)
+    roofline = mark_roofline(n, float(ph[0]), args.traffic_json)
     roofline["step_share"] = round(roofline["kernel_ms"] / (dt * 1e3), 4)
     log("mark: %s" % roofline)
 

@@ -123,8 +123,8 @@ int seqcdc_plan_stats(seqcdc_plan* plan, uint64_t* out3);
 
 /* Per-phase timing of the plan's calls (off by default; on adds HIP events
  * to every call).  seqcdc_plan_phase_ms waits for the plan's last timed call
- * and writes 4 durations in milliseconds.  Mode 0: the mark kernel (with the
- * clearing of the work counters before it), pass A (speculative chains),
+ * and writes 4 durations in milliseconds.  Mode 0: the mark kernel (events
+ * right before and after its launch), pass A (speculative chains),
  * pass B (continuations), stitch + compaction.  Mode 1: the pipeline kernel
  * (with the clearing before it), 0, the resume kernel (continuations the
  * pipeline left), stitch + compaction.  Overlapped batches: the marking of
@@ -176,6 +176,29 @@ typedef struct {
 int seqcdc_chunk_batch(seqcdc_plan* plan, const seqcdc_file* h_files, uint32_t nfiles, const seqcdc_params* h_params,
                        uint32_t nparams, uint64_t* d_cuts, const uint64_t* h_cut_offsets, uint64_t* d_counts,
                        void* stream);
+
+/* Prepared batches, for callers that chunk the same set of device buffers
+ * again and again (a ring of staging buffers refilled with new data, a fixed
+ * set of volumes).  seqcdc_batch_prepare lays the batch out once, in a
+ * workspace the batch owns, runs it once (synchronously), and captures its
+ * launch sequence (kernels only: counter clearing, mark, pass A, pass B,
+ * stitch, compaction) into a hipGraph.  seqcdc_batch_launch replays the graph
+ * on `stream`: the files' current contents are chunked into the same d_cuts /
+ * d_counts, with no host-side work beyond the graph launch; the results are
+ * those seqcdc_chunk_batch gives.  Arguments are those of seqcdc_chunk_batch
+ * and stay owned by the caller; the file pointers, lengths, parameters and
+ * output arrays are fixed at preparation and must stay valid until the batch
+ * is destroyed.  `settings` (may be NULL) supplies tuning choices and the
+ * resolve mode; overlapped groups are not used.  Launches of one batch run
+ * one after the other, whatever their streams (each waits for the previous
+ * one).  seqcdc_batch_destroy waits for the last launch.  Errors as for
+ * seqcdc_chunk_batch; nfiles must be at least 1. */
+typedef struct seqcdc_batch seqcdc_batch;
+int seqcdc_batch_prepare(seqcdc_plan* settings, const seqcdc_file* files, uint32_t nfiles,
+                         const seqcdc_params* params, uint32_t nparams, uint64_t* d_cuts,
+                         const uint64_t* h_cut_offsets, uint64_t* d_counts, seqcdc_batch** out);
+int seqcdc_batch_launch(seqcdc_batch* batch, void* stream);
+int seqcdc_batch_destroy(seqcdc_batch* batch);
 
 /* The mark step alone (Sec. III-D masks), for inspection and tests.
  * d_eo receives 4 * ceil(n/64) uint32 words: byte q belongs to group q/64;

@@ -80,6 +80,10 @@ _SIGS = {
                           ctypes.c_int),
     "seqcdc_chunk_batch": ([_p, ctypes.POINTER(seqcdc_file), _u32, ctypes.POINTER(seqcdc_params), _u32, _p,
                             ctypes.POINTER(_u64), _p, _p], ctypes.c_int),
+    "seqcdc_batch_prepare": ([_p, ctypes.POINTER(seqcdc_file), _u32, ctypes.POINTER(seqcdc_params), _u32, _p,
+                              ctypes.POINTER(_u64), _p, ctypes.POINTER(_p)], ctypes.c_int),
+    "seqcdc_batch_launch": ([_p, _p], ctypes.c_int),
+    "seqcdc_batch_destroy": ([_p], ctypes.c_int),
     "seqcdc_mark": ([_p, _u64, ctypes.POINTER(seqcdc_params), _p, _p], ctypes.c_int),
     "seqcdc_chunk_host": ([_p, _u64, ctypes.POINTER(seqcdc_params), _p, _u64, ctypes.POINTER(_u64)], ctypes.c_int),
     "seqcdc_dedup_stats": ([ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_u64), _u32,
@@ -265,6 +269,29 @@ def seqcdc_chunk_batch(files, params_list, d_cuts, cut_offsets, d_counts, stream
         raise ValueError("cut_offsets needs nfiles + 1 entries")
     _check(lib.seqcdc_chunk_batch(plan, farr, nf, parr, len(params_list), d_cuts, offs, d_counts,
                                   _stream_handle(stream)))
+
+
+def seqcdc_batch_prepare(files, params_list, d_cuts, cut_offsets, d_counts, settings=None):
+    """A prepared (hipGraph-captured) batch; arguments as for seqcdc_chunk_batch.  Returns the handle."""
+    if isinstance(files, ctypes.Array):
+        farr, nf = files, getattr(files, "_len", len(files))
+    else:
+        farr = file_table([f[0] for f in files], [f[1] for f in files], [f[2] for f in files])
+        nf = len(files)
+    parr = (seqcdc_params * max(len(params_list), 1))(*[_as_params(p) for p in params_list])
+    offs = cut_offsets if isinstance(cut_offsets, ctypes.Array) else offsets_table(cut_offsets)
+    h = _p()
+    _check(lib.seqcdc_batch_prepare(settings, farr, nf, parr, len(params_list), d_cuts, offs, d_counts,
+                                    ctypes.byref(h)))
+    return h
+
+
+def seqcdc_batch_launch(batch, stream=None):
+    _check(lib.seqcdc_batch_launch(batch, _stream_handle(stream)))
+
+
+def seqcdc_batch_destroy(batch):
+    _check(lib.seqcdc_batch_destroy(batch))
 
 
 def seqcdc_mark(d_stream, n, params, d_eo, stream=None):

@@ -235,16 +235,6 @@ void plan_free(Plan* pl) {
   if (pl->upload_done) (void)hipEventDestroy(pl->upload_done);
 }
 
-// A stream of the batch, before device pointers are assigned.
-struct Spec {
-  const uint8_t* data;
-  u64 n;
-  const seqcdc_params* p;
-  u64* out;
-  u64 out_cap;
-  u64* out_count;
-};
-
 template <class T>
 static T* carve(char*& cur, size_t count) {
   cur = (char*)round_up((u64)cur, 256);
@@ -287,7 +277,7 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   if (nfiles == 0) return SEQCDC_OK;
   HIP_TRY(hipSetDevice(pl->device));
   // The plan's buffers are reused: a call on another stream must wait for the previous call.
-  if (pl->pending && pl->last_stream != st) HIP_TRY(hipStreamWaitEvent(st, pl->call_done, 0));
+  if (!pl->capturing && pl->pending && pl->last_stream != st) HIP_TRY(hipStreamWaitEvent(st, pl->call_done, 0));
 
   // ---- host-side layout
   // Overlapped batches take the files largest first and cut them into groups
@@ -450,7 +440,7 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   }
 
   // ---- stage tables (pinned) and upload
-  if (pl->upload_pending) {
+  if (pl->upload_pending && !pl->capturing) {
     HIP_TRY(hipEventSynchronize(pl->upload_done));
     pl->upload_pending = false;
   }
@@ -489,9 +479,11 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
     for (u64 i = (lo + kHintSpans - 1) / kHintSpans; i * kHintSpans < hi; i++) h_hint[i] = f;
   }
   auto dev = [&](void* hp) { return (void*)(dbase + ((char*)hp - h)); };
-  HIP_TRY(hipMemcpyAsync(dbase, h, used, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipEventRecord(pl->upload_done, st));
-  pl->upload_pending = true;
+  if (!pl->capturing) {  // a capture replays tables uploaded by an identical eager call
+    HIP_TRY(hipMemcpyAsync(dbase, h, used, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(pl->upload_done, st));
+    pl->upload_pending = true;
+  }
 
   const FileDesc* d_files = (const FileDesc*)dev(h_files);
   const u32* d_hint = (const u32*)dev(h_hint);
@@ -552,8 +544,8 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
     HIP_TRY(timing_mark(pl, 4, st));
   } else if (G == 1) {
     const u32 groups = std::max<u32>(1, pl->cus * waves / kWavesPerGroup);  // 4 independent waves each
-    HIP_TRY(timing_mark(pl, 0, st));
     HIP_TRY(launch_clear(heads, 64, st));
+    HIP_TRY(timing_mark(pl, 0, st));  // the mark phase is the mark kernel alone
     HIP_TRY(launch_mark(d_files, d_hint, 0, spans, U, st));
     HIP_TRY(timing_mark(pl, 1, st));
     HIP_TRY(launch_chains(d_files, ws, (const u32*)dev(h_order), nchains, heads,
@@ -619,9 +611,11 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
     HIP_TRY(hipEventRecord(pl->ev_join, sb));
     HIP_TRY(hipStreamWaitEvent(st, pl->ev_join, 0));
   }
-  HIP_TRY(hipEventRecord(pl->call_done, st));
-  pl->pending = true;
-  pl->last_stream = st;
+  if (!pl->capturing) {
+    HIP_TRY(hipEventRecord(pl->call_done, st));
+    pl->pending = true;
+    pl->last_stream = st;
+  }
   pl->last_nchains = nchains;
   pl->last_multi = (u32)multi.size();
   return SEQCDC_OK;
@@ -678,14 +672,13 @@ int chunk_plan(Plan* pl, const void* d_stream, u64 n, const seqcdc_params* p, u6
   return SEQCDC_OK;
 }
 
-int chunk_batch(Plan* pl, const seqcdc_file* files, u32 nfiles, const seqcdc_params* params, u32 nparams,
-                u64* d_cuts, const u64* h_off, u64* d_counts, hipStream_t st) {
-  if (nfiles == 0) return SEQCDC_OK;
+int build_specs(const seqcdc_file* files, u32 nfiles, const seqcdc_params* params, u32 nparams, u64* d_cuts,
+                const u64* h_off, u64* d_counts, std::vector<Spec>& specs) {
   if (!files || !params || !h_off || !d_counts || !d_cuts) return fail(SEQCDC_EINVAL, "NULL argument");
   int rc;
   for (u32 i = 0; i < nparams; i++)
     if ((rc = validate(&params[i]))) return rc;
-  std::vector<Spec> specs(nfiles);
+  specs.resize(nfiles);
   for (u32 f = 0; f < nfiles; f++) {
     const seqcdc_file& F = files[f];
     if (F.params_index >= nparams) return fail(SEQCDC_EINVAL, "file %u: params_index out of range", f);
@@ -699,6 +692,15 @@ int chunk_batch(Plan* pl, const seqcdc_file* files, u32 nfiles, const seqcdc_par
                   (unsigned long long)max_cuts(F.n, p));
     specs[f] = Spec{(const uint8_t*)F.d_data, F.n, p, d_cuts + h_off[f], room, d_counts + f};
   }
+  return SEQCDC_OK;
+}
+
+int chunk_batch(Plan* pl, const seqcdc_file* files, u32 nfiles, const seqcdc_params* params, u32 nparams,
+                u64* d_cuts, const u64* h_off, u64* d_counts, hipStream_t st) {
+  if (nfiles == 0) return SEQCDC_OK;
+  std::vector<Spec> specs;
+  int rc;
+  if ((rc = build_specs(files, nfiles, params, nparams, d_cuts, h_off, d_counts, specs))) return rc;
   std::lock_guard<std::mutex> g(pl->mu);
   return run_batch(pl, specs.data(), nfiles, st, false);
 }

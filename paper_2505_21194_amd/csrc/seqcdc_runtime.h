@@ -4,6 +4,7 @@
 
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/seqcdc.h"
 #include "seqcdc_internal.h"
@@ -78,6 +79,19 @@ struct Plan {
   u32 waves_for(const seqcdc_params* p) const;
   int mode_for(const seqcdc_params* p) const;
   u32 groups_for(u32 nfiles, u64 total) const;
+  // set while a prepared batch captures its launch sequence: no uploads, host
+  // waits or bookkeeping events (the tables are already on the device)
+  bool capturing = false;
+};
+
+// A stream of a batch, before device pointers are assigned.
+struct Spec {
+  const uint8_t* data;
+  u64 n;
+  const seqcdc_params* p;
+  u64* out;
+  u64 out_cap;
+  u64* out_count;
 };
 
 int fail(int code, const char* fmt, ...);
@@ -90,6 +104,9 @@ int chunk_plan(Plan* pl, const void* d_stream, u64 n, const seqcdc_params* p, u6
                hipStream_t st);
 int chunk_batch(Plan* pl, const seqcdc_file* files, u32 nfiles, const seqcdc_params* params, u32 nparams,
                 u64* d_cuts, const u64* h_off, u64* d_counts, hipStream_t st);
+int build_specs(const seqcdc_file* files, u32 nfiles, const seqcdc_params* params, u32 nparams, u64* d_cuts,
+                const u64* h_off, u64* d_counts, std::vector<Spec>& specs);
+int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark_only);
 TuneKey plan_key(const Plan* pl, const seqcdc_params* p);
 bool tune_lookup(const TuneKey& k, TuneEntry* out);
 void tune_store(const TuneEntry& e);

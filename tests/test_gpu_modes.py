@@ -167,3 +167,52 @@ def test_many_small_files(env, mode):
         seq.seqcdc_plan_destroy(plan)
     for i, (x, o) in enumerate(zip(datas, outs)):
         assert np.array_equal(o.cpu().numpy().astype(np.uint64), oracle.chunk(x, **p)), i
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_prepared_batch_graph_replays(env, mode):
+    """A prepared (hipGraph-captured) batch: each replay, with new input contents and eager work in between,
+    equals the oracle."""
+    torch, seq = env
+    rng = np.random.default_rng(123 + mode)
+    sizes = [int(x) for x in rng.integers(0, 2 << 20, 20)] + [0, 1, 6 << 20]
+    params = [P(), P(mode=1, sl=6, mn=8192, mx=32768, skip=512)]
+    pidx = [i % 2 for i in range(len(sizes))]
+    bufs = [torch.zeros(max(s, 1), dtype=torch.uint8, device="cuda") for s in sizes]
+    ps = [seq.make_params(**p) for p in params]
+    offs = [0]
+    for s, pi in zip(sizes, pidx):
+        offs.append(offs[-1] + max(seq.seqcdc_max_cuts(s, ps[pi]), 1))
+    cuts = torch.zeros(offs[-1], dtype=torch.int64, device="cuda")
+    counts = torch.zeros(len(sizes), dtype=torch.int64, device="cuda")
+    ftab = seq.file_table([b.data_ptr() for b in bufs], sizes, pidx)
+    settings = seq.seqcdc_plan_create()
+    seq.seqcdc_plan_set_tuning(settings, segment_bytes=128 << 10)
+    seq.seqcdc_plan_set_mode(settings, mode)
+    other = seq.seqcdc_plan_create()
+    _say("prepare graph batch, mode", mode)
+    batch = seq.seqcdc_batch_prepare(ftab, ps, cuts.data_ptr(), offs, counts.data_ptr(), settings=settings)
+    try:
+        for rep in range(3):
+            datas = [synth.mixed(s, seed=5000 + 100 * rep + i) for i, s in enumerate(sizes)]
+            for b, d in zip(bufs, datas):  # new contents, same buffers
+                if d.size:
+                    b[:d.size].copy_(torch.from_numpy(d))
+            cuts.zero_()
+            counts.zero_()
+            # eager work of the program's own between replays
+            eager = seq.chunk_batch([b[:s] for b, s in zip(bufs, sizes)], params, params_index=pidx, plan=other)
+            torch.cuda.synchronize()
+            _say("replay", rep)
+            seq.seqcdc_batch_launch(batch)
+            torch.cuda.synchronize()
+            cnt = counts.cpu().numpy()
+            for i, (d, s) in enumerate(zip(datas, sizes)):
+                want = oracle.chunk(d, **params[pidx[i]])
+                got = cuts[offs[i]:offs[i] + int(cnt[i])].cpu().numpy().astype(np.uint64)
+                assert np.array_equal(got, want), (rep, i)
+                assert np.array_equal(eager[i].cpu().numpy().astype(np.uint64), want), (rep, i)
+    finally:
+        seq.seqcdc_batch_destroy(batch)
+        seq.seqcdc_plan_destroy(settings)
+        seq.seqcdc_plan_destroy(other)
