@@ -1,0 +1,118 @@
+"""Parity at the full sizes of the benchmark workloads, whole outputs against the oracle.
+
+* One 1 GiB mixed backup-like stream (1 MiB blocks: uniform, Zipf text, zero / repeated-pattern runs), both
+  modes, 8 / 16 / 32 KiB averages (Table I), with the default plan (the configuration bench.py times).
+* A 256 MiB uniform base plus 9 versions of 200 seeded edits each, chunked in one batch at 4..64 KiB averages:
+  every boundary list and the space savings of Eq. 1.
+* 4096 files with log-normal sizes (median 256 KiB, sigma 1.5, 4 KiB..64 MiB), each a mixed stream of its own
+  seed, at a 16 KiB average: the eager batched call and its prepared hipGraph replay.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2505_21194_amd as seq
+    return torch, seq
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _pd(p):
+    return dict(mode=p.mode, seq_length=p.seq_length, min_size=p.min_size, max_size=p.max_size,
+                skip_trigger=p.skip_trigger, skip_size=p.skip_size)
+
+
+@pytest.fixture(scope="module")
+def stream_1g(env):
+    torch, seq = env
+    host = synth.mixed(1 << 30, seed=2)
+    return host, torch.from_numpy(host).cuda()
+
+
+@pytest.mark.parametrize("avg_kib", [8, 16, 32])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_plain_1gib_mixed(env, stream_1g, avg_kib, mode):
+    torch, seq = env
+    host, dev = stream_1g
+    p = seq.seqcdc_params_for_avg(avg_kib << 10)
+    p.mode = mode
+    _say("plain 1 GiB mixed, avg", avg_kib, "KiB, mode", mode)
+    got = seq.chunk(dev, p).cpu().numpy().astype(np.uint64)
+    want = oracle.chunk(host, **_pd(p))
+    assert got.size == want.size and np.array_equal(got, want)
+
+
+@pytest.fixture(scope="module")
+def snapshots(env):
+    torch, seq = env
+    vers = synth.snapshot_series(256 << 20, 10, seed=0, nedits=200, maxlen=4096)
+    return vers, [torch.from_numpy(v).cuda() for v in vers]
+
+
+@pytest.mark.parametrize("avg_kib", [4, 8, 16, 32, 64])
+def test_snapshot_series_full(env, snapshots, avg_kib):
+    torch, seq = env
+    vers, devs = snapshots
+    p = seq.seqcdc_params_for_avg(avg_kib << 10)
+    _say("snapshot series 10 x 256 MiB, avg", avg_kib, "KiB")
+    outs = [o.cpu().numpy().astype(np.uint64) for o in seq.chunk_batch(devs, [p])]
+    want = [oracle.chunk(v, **_pd(p)) for v in vers]
+    for i, (g, w) in enumerate(zip(outs, want)):
+        assert g.size == w.size and np.array_equal(g, w), i
+    got = seq.seqcdc_dedup_stats(vers, outs)
+    ref = oracle.dedup_stats(vers, want)
+    assert got[0] == ref[0] and got[1] == ref[1]
+    assert got[2] == pytest.approx(ref[2], abs=1e-12) and got[3] == pytest.approx(ref[3], rel=1e-12)
+
+
+def test_batched_4096_files(env):
+    torch, seq = env
+    nfiles = 4096
+    sizes = synth.lognormal_sizes(nfiles, 256 * 1024, 1.5, 4096, 64 << 20, seed=4).astype(np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    host = np.empty(int(offs[-1]), np.uint8)
+    for f in range(nfiles):
+        host[int(offs[f]):int(offs[f + 1])] = synth.mixed(int(sizes[f]), seed=100000 + f)
+    buf = torch.from_numpy(host).cuda()
+    p = seq.seqcdc_params_for_avg(16384)
+    cut_offs = [0]
+    for s in sizes:
+        cut_offs.append(cut_offs[-1] + seq.seqcdc_max_cuts(int(s), p))
+    cuts = torch.zeros(cut_offs[-1], dtype=torch.int64, device="cuda")
+    counts = torch.zeros(nfiles, dtype=torch.int64, device="cuda")
+    ftab = seq.file_table([buf.data_ptr() + int(offs[f]) for f in range(nfiles)], sizes)
+    want = [oracle.chunk(host[int(offs[f]):int(offs[f + 1])], **_pd(p)) for f in range(nfiles)]
+
+    def check(label):
+        torch.cuda.synchronize()
+        cnt = counts.cpu().numpy()
+        allc = cuts.cpu().numpy().astype(np.uint64)
+        for f in range(nfiles):
+            got = allc[cut_offs[f]:cut_offs[f] + int(cnt[f])]
+            assert np.array_equal(got, want[f]), (label, f)
+
+    _say("batched 4096 files, eager")
+    seq.seqcdc_chunk_batch(ftab, [p], cuts.data_ptr(), cut_offs, counts.data_ptr())
+    check("eager")
+    cuts.zero_()
+    counts.zero_()
+    _say("batched 4096 files, prepared graph")
+    b = seq.seqcdc_batch_prepare(ftab, [p], cuts.data_ptr(), cut_offs, counts.data_ptr())
+    try:
+        cuts.zero_()
+        counts.zero_()
+        seq.seqcdc_batch_launch(b)
+        check("graph")
+    finally:
+        seq.seqcdc_batch_destroy(b)
