@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the library's autotuner (default settings)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="oracle work to time on the host")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run a 1 GiB device copy and the mark kernel (for rocprofv3 --pmc runs)")
@@ -72,7 +73,7 @@ def mark_roofline(n, kernel_ms, traffic_json):
             "kernel_ms": round(ms, 4), "alg_bytes_per_launch": alg}
 
 
-def batched(seq, torch, stream, plan, steps, warmup, dev):
+def batched(seq, torch, stream, plan, steps, warmup, dev, tune):
     import synth
     nfiles = 4096
     sizes = synth.lognormal_sizes(nfiles, 256 * 1024, 1.5, 4096, 64 << 20, seed=4).astype(np.int64)
@@ -94,6 +95,13 @@ def batched(seq, torch, stream, plan, steps, warmup, dev):
 
     def bstep():
         seq.seqcdc_chunk_batch(ftab, [pb], bcuts.data_ptr(), otab, bcounts.data_ptr(), stream=stream, plan=plan)
+
+    tuning = None
+    if tune:  # the autotuner on the batch's bytes taken as one stream, at the batch's parameters (untimed)
+        seq.seqcdc_autotune(plan, buf.data_ptr(), total, pb, stream=stream)
+        seg, span, waves = seq.seqcdc_plan_get_tuning(plan, total, pb)
+        tuning = {"segment_bytes": seg, "mark_span_blocks": span, "waves_per_cu": waves}
+        log("batched tuning: %s" % tuning)
 
     for _ in range(warmup):
         bstep()
@@ -134,7 +142,8 @@ def batched(seq, torch, stream, plan, steps, warmup, dev):
             "graph_ms_per_step": round(gdt * 1e3, 3), "graph_GBps": round(total / gdt / 1e9, 1),
             "graph_counts_match": graph_same,
             "per_file_launch_GBps": round(total / pdt / 1e9, 2), "speedup_vs_per_file": round(pdt / bdt, 2),
-            "params": "avg 16 KiB: SeqLength 5, SkipTrigger 50, SkipSize 512, min 8 KiB, max 32 KiB"}
+            "params": "avg 16 KiB: SeqLength 5, SkipTrigger 50, SkipSize 512, min 8 KiB, max 32 KiB",
+            "tuning": tuning}
 
 
 def serving(seq, torch, dev):
@@ -263,6 +272,12 @@ def main():
     cuts = torch.empty(cap, dtype=torch.int64, device=dev)
     plan = seq.seqcdc_plan_create()
     torch.cuda.synchronize()
+    tuning = None
+    if not args.no_tune:  # the library's autotuner, on the stream itself (untimed)
+        seq.seqcdc_autotune(plan, d.data_ptr(), n, p, stream=stream)
+        seg, span, waves = seq.seqcdc_plan_get_tuning(plan, n, p)
+        tuning = {"segment_bytes": seg, "mark_span_blocks": span, "waves_per_cu": waves}
+        log("plain tuning: %s" % tuning)
 
     def step():
         return seq.seqcdc_chunk(d.data_ptr(), n, p, cuts.data_ptr(), cap, stream=stream, plan=plan)
@@ -297,7 +312,7 @@ def main():
 
     extra = {"phases_ms": phases}
     if not args.no_batch:
-        extra["batched"] = batched(seq, torch, stream, plan, args.steps, args.warmup, dev)
+        extra["batched"] = batched(seq, torch, stream, plan, args.steps, args.warmup, dev, not args.no_tune)
         log("batched: %s" % extra["batched"])
     if not args.no_serve:
         extra["serving"] = serving(seq, torch, dev)
@@ -314,7 +329,8 @@ def main():
            "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u8", "data": "synthetic",
            "config": {"workload": "plain %d MiB mixed backup-like stream, Increasing, avg 8 KiB (Table I)"
-                                  % args.size_mib, "bytes": n, "cuts": count, "parallelism": "single GPU"},
+                                  % args.size_mib, "bytes": n, "cuts": count, "parallelism": "single GPU",
+                      "tuning": tuning},
            "roofline": roofline, "cpu_baseline": cpu}
     out.update(extra)
     print(json.dumps(out), flush=True)

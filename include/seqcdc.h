@@ -81,10 +81,10 @@ int seqcdc_plan_destroy(seqcdc_plan* plan);
 
 /* Tuning knobs of a plan (0 = keep).  segment_bytes: length of the segments
  * a stream is split into for speculative resolution (rounded up to a whole
- * number of mark spans); mark_span_blocks: 1 KiB blocks per mark span, the
+ * number of mark spans; default 128 x min_size, at least 64 KiB); mark_span_blocks: 1 KiB blocks per mark span, the
  * unit of marking work (4, 8, 16, 32 or 64); waves_per_cu: waves per compute
  * unit of the persistent chain kernels, one chain per wave (4..32, a
- * multiple of 4; default 16; each wave keeps 8 KiB of windows in LDS, so at
+ * multiple of 4; default 8; each wave keeps 8 KiB of windows in LDS, so at
  * most 20 are resident per compute unit). */
 int seqcdc_plan_set_tuning(seqcdc_plan* plan, uint64_t segment_bytes, uint32_t mark_span_blocks,
                            uint32_t waves_per_cu);

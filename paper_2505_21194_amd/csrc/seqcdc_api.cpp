@@ -167,7 +167,7 @@ u64 Plan::segment_for(u64 n, const seqcdc_params* p) const {
   if (!seg) {
     TuneEntry te;
     if (tune_lookup(plan_key(this, p), &te)) seg = te.seg_mult * p->min_size;
-    else seg = 256 * p->min_size;
+    else seg = 128 * p->min_size;
   }
   seg = std::max<u64>(seg, 64 * 1024);
   if (n / seg > kMaxSegments) seg = n / kMaxSegments + 1;
@@ -185,7 +185,7 @@ u32 Plan::waves_for(const seqcdc_params* p) const {
   if (waves_override) return waves_override;
   TuneEntry te;
   if (p && tune_lookup(plan_key(this, p), &te)) return te.waves_per_cu;
-  return 16;
+  return 8;
 }
 
 // Overlapped batches are off unless asked for: on MI355X the chains that run

@@ -65,6 +65,24 @@ __device__ __forceinline__ u32 wave_incl_scan(u32 v) {
   return v;
 }
 
+// 64-bit inclusive prefix sum across the wave: the same DPP steps on both
+// halves, with the carry out of the low half added to the high half.
+__device__ __forceinline__ u64 wave_incl_scan64(u64 v) {
+  u32 lo = (u32)v, hi = (u32)(v >> 32);
+  auto step = [&](u32 slo, u32 shi) {
+    const u32 nlo = lo + slo;
+    hi += shi + (nlo < lo ? 1u : 0u);
+    lo = nlo;
+  };
+  step(__builtin_amdgcn_update_dpp(0u, lo, 0x111, 0xf, 0xf, true), __builtin_amdgcn_update_dpp(0u, hi, 0x111, 0xf, 0xf, true));
+  step(__builtin_amdgcn_update_dpp(0u, lo, 0x112, 0xf, 0xf, true), __builtin_amdgcn_update_dpp(0u, hi, 0x112, 0xf, 0xf, true));
+  step(__builtin_amdgcn_update_dpp(0u, lo, 0x114, 0xf, 0xf, true), __builtin_amdgcn_update_dpp(0u, hi, 0x114, 0xf, 0xf, true));
+  step(__builtin_amdgcn_update_dpp(0u, lo, 0x118, 0xf, 0xf, true), __builtin_amdgcn_update_dpp(0u, hi, 0x118, 0xf, 0xf, true));
+  step(__builtin_amdgcn_update_dpp(0u, lo, 0x142, 0xa, 0xf, false), __builtin_amdgcn_update_dpp(0u, hi, 0x142, 0xa, 0xf, false));
+  step(__builtin_amdgcn_update_dpp(0u, lo, 0x143, 0xc, 0xf, false), __builtin_amdgcn_update_dpp(0u, hi, 0x143, 0xc, 0xf, false));
+  return (u64)lo | ((u64)hi << 32);
+}
+
 // Takes the next index of a work counter for the whole wave.  Every lane
 // executes the atomic (lane 0 adds 1, the others 0), so no branch surrounds it
 // and the value lane 0 receives is read back in the same straight-line code.

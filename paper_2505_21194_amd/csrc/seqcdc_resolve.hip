@@ -652,30 +652,36 @@ __global__ __launch_bounds__(256) void clear_kernel(u32* p, u64 count) {
 // Stitch and compaction
 // ---------------------------------------------------------------------------
 
-// Block-wide exclusive scan of one value per thread (256 threads).
+constexpr u32 kStitchThreads = 1024;  // 16 waves
+constexpr u32 kStitchWaves = kStitchThreads / 64;
+
+// Workgroup-wide exclusive scan of one 64-bit value per thread
+// (kStitchThreads threads): a DPP scan inside each wave, then the wave totals
+// through LDS.  Two barriers; *total receives the sum over the workgroup.
 __device__ u64 block_exclusive_scan(u64 v, u64* sh, u64& total) {
-  const u32 t = threadIdx.x;
-  sh[t] = v;
+  const u32 w = threadIdx.x >> 6;
+  const u64 incl = wave_incl_scan64(v);
+  if (lane_id() == 63) sh[w] = incl;
   __syncthreads();
-  for (u32 d = 1; d < 256; d <<= 1) {
-    u64 a = t >= d ? sh[t - d] : 0;
-    __syncthreads();
-    sh[t] += a;
-    __syncthreads();
+  u64 pre = 0, tot = 0;
+#pragma unroll
+  for (u32 i = 0; i < kStitchWaves; i++) {
+    const u64 x = sh[i];
+    pre += i < w ? x : 0ull;
+    tot += x;
   }
-  total = sh[255];
-  u64 r = sh[t] - v;
-  __syncthreads();
-  return r;
+  total = tot;
+  __syncthreads();  // sh is reused by the next scan
+  return pre + incl - v;
 }
 
-// Stitch (one 256-thread workgroup per multi-segment file): the exact cut
-// sequence starts in chain 0 and moves to chain conv_chain[k] at conv_val[k].
-// Chains strictly between k and conv_chain[k] are covered by k's
-// continuation and contribute nothing.
-__global__ __launch_bounds__(256) void stitch_kernel(const FileDesc* __restrict__ files, ChainWs ws,
-                                                     const u32* __restrict__ multi, u32 nmulti) {
-  __shared__ u64 sh[256];
+// Stitch (one workgroup per multi-segment file): the exact cut sequence
+// starts in chain 0 and moves to chain conv_chain[k] at conv_val[k].  Chains
+// strictly between k and conv_chain[k] are covered by k's continuation and
+// contribute nothing.
+__global__ __launch_bounds__(kStitchThreads) void stitch_kernel(const FileDesc* __restrict__ files, ChainWs ws,
+                                                                const u32* __restrict__ multi, u32 nmulti) {
+  __shared__ u64 sh[kStitchWaves];
   __shared__ u32 s_nj, s_nr;
   const u32 t = threadIdx.x;
   const FileDesc& F = files[multi[blockIdx.x]];
@@ -688,16 +694,16 @@ __global__ __launch_bounds__(256) void stitch_kernel(const FileDesc* __restrict_
   u32* cov = ws.covered + 2 * (u64)c0;
 
   // 1. boundaries whose continuation skipped at least one whole segment
-  u64 base = 0;
-  for (u32 j0 = 0; j0 < nseg; j0 += 256) {
+  u32 base = 0;
+  for (u32 j0 = 0; j0 < nseg; j0 += kStitchThreads) {
     const u32 k = j0 + t;
     const bool jump = k + 1 < nseg && ws.conv_chain[c0 + k] != k + 1;
     u64 tot;
-    const u64 pos = block_exclusive_scan(jump ? 1 : 0, sh, tot);
+    const u32 pos = (u32)block_exclusive_scan(jump ? 1u : 0u, sh, tot);
     if (jump) jumps[base + pos] = k;
-    base += tot;
+    base += (u32)tot;
   }
-  if (t == 0) s_nj = (u32)base;
+  if (t == 0) s_nj = base;
   __syncthreads();
 
   // 2. walk the jumps in order; a jump from an active chain covers (k, next)
@@ -718,7 +724,7 @@ __global__ __launch_bounds__(256) void stitch_kernel(const FileDesc* __restrict_
   const u32 nr = s_nr;
 
   // 3. active flags; 4. entry index of each active chain
-  for (u32 j = t; j < nseg; j += 256) {
+  for (u32 j = t; j < nseg; j += kStitchThreads) {
     u32 lo = 0, hi = nr;  // first range with start > j
     while (lo < hi) {
       u32 mid = (lo + hi) >> 1;
@@ -730,7 +736,7 @@ __global__ __launch_bounds__(256) void stitch_kernel(const FileDesc* __restrict_
     if (j == 0) ws.entry_idx[c0] = 0;
   }
   __syncthreads();
-  for (u32 k = t; k + 1 < nseg; k += 256) {
+  for (u32 k = t; k + 1 < nseg; k += kStitchThreads) {
     if (!ws.active[c0 + k]) continue;
     const u32 nx = ws.conv_chain[c0 + k];
     if (nx < nseg) ws.entry_idx[c0 + nx] = ws.conv_idx[c0 + k];
@@ -738,8 +744,8 @@ __global__ __launch_bounds__(256) void stitch_kernel(const FileDesc* __restrict_
   __syncthreads();
 
   // 5. output count of each chain; 6. offsets
-  base = 0;
-  for (u32 j0 = 0; j0 < nseg; j0 += 256) {
+  u64 obase = 0;
+  for (u32 j0 = 0; j0 < nseg; j0 += kStitchThreads) {
     const u32 j = j0 + t;
     u64 cnt = 0;
     if (j < nseg && ws.active[c0 + j]) {
@@ -752,10 +758,10 @@ __global__ __launch_bounds__(256) void stitch_kernel(const FileDesc* __restrict_
     }
     u64 tot;
     const u64 pos = block_exclusive_scan(cnt, sh, tot);
-    if (j < nseg) ws.out_off[c0 + j] = base + pos;
-    base += tot;
+    if (j < nseg) ws.out_off[c0 + j] = obase + pos;
+    obase += tot;
   }
-  if (t == 0) *F.out_count = base;
+  if (t == 0) *F.out_count = obase;
 }
 
 // Compaction: one wave per chain of a multi-segment file copies its exact
@@ -850,7 +856,7 @@ hipError_t launch_resume(const FileDesc* d_files, const ChainWs& ws, u32* resume
 
 hipError_t launch_stitch(const FileDesc* d_files, const ChainWs& ws, const u32* d_multi, u32 nmulti, hipStream_t st) {
   if (!nmulti) return hipSuccess;
-  hipLaunchKernelGGL(stitch_kernel, dim3(nmulti), dim3(256), 0, st, d_files, ws, d_multi, nmulti);
+  hipLaunchKernelGGL(stitch_kernel, dim3(nmulti), dim3(kStitchThreads), 0, st, d_files, ws, d_multi, nmulti);
   return hipGetLastError();
 }
 

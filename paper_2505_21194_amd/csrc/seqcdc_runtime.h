@@ -40,7 +40,7 @@ struct TuneKey {
 
 struct TuneEntry {
   TuneKey key;
-  u64 seg_mult = 256;  // segment length = seg_mult * min_size
+  u64 seg_mult = 128;  // segment length = seg_mult * min_size
   u32 span_blocks = 8;
   u32 waves_per_cu = 8;
   int mode = 0;
