@@ -26,6 +26,7 @@ struct Batch {
 
 static void batch_free(Batch* b) {
   if (b->launched) (void)hipEventSynchronize(b->done);
+  if (b->cap) (void)hipStreamSynchronize(b->cap);  // a preparation that failed half-way may have work in flight
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);

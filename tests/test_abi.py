@@ -85,3 +85,29 @@ def test_dedup_stats_matches_oracle(seq):
     assert got[0] == want[0] and got[1] == want[1]
     assert got[2] == pytest.approx(want[2], abs=0, rel=1e-15)
     assert want[2] > 0.5  # four near-identical versions deduplicate well
+
+
+def test_new_entry_points_reject_bad_arguments_without_gpu_work(seq):
+    """Plan knobs, prepared batches and diagnostics check their arguments before touching a device."""
+    E = seq.SEQCDC_EINVAL
+    assert seq.lib.seqcdc_plan_set_overlap(None, 2) == E
+    assert seq.lib.seqcdc_plan_set_mode(None, 0) == E
+    assert seq.lib.seqcdc_plan_set_timing(None, 1) == E
+    assert seq.lib.seqcdc_plan_stats(None, None) == E
+    assert seq.lib.seqcdc_plan_phase_ms(None, None) == E
+    assert seq.lib.seqcdc_batch_launch(None, None) == E
+    assert seq.lib.seqcdc_batch_destroy(None) == E
+    out = ctypes.c_void_p(123)
+    p = seq.make_params()
+    f = (seq.seqcdc_file * 1)(seq.seqcdc_file(None, 0, 0, 0))
+    offs = (ctypes.c_uint64 * 2)(0, 1)
+    # no output handle; no files
+    assert seq.lib.seqcdc_batch_prepare(None, f, 1, ctypes.byref(p), 1, None, offs, None, None) == E
+    assert seq.lib.seqcdc_batch_prepare(None, f, 0, ctypes.byref(p), 1, None, offs, None, ctypes.byref(out)) == E
+    assert out.value is None  # cleared on failure
+    # NULL outputs, bad params index
+    assert seq.lib.seqcdc_batch_prepare(None, f, 1, ctypes.byref(p), 1, None, offs, None, ctypes.byref(out)) == E
+    f2 = (seq.seqcdc_file * 1)(seq.seqcdc_file(None, 0, 5, 0))
+    assert seq.lib.seqcdc_batch_prepare(None, f2, 1, ctypes.byref(p), 1, ctypes.c_void_p(16), offs, ctypes.c_void_p(16),
+                                        ctypes.byref(out)) == E
+    assert "params_index" in seq.last_error()
