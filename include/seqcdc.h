@@ -99,7 +99,11 @@ int seqcdc_plan_get_tuning(seqcdc_plan* plan, uint64_t n, const seqcdc_params* p
  * the input are still being marked and each chain continues past its segment
  * as soon as the next chain's cut list exists; every published span costs an
  * L2 write-back on its XCD, which makes this mode slower on MI355X at the
- * sizes measured so far.  Both give the same cuts. */
+ * sizes measured so far.  2: the mark kernel, then one persistent pipeline
+ * kernel of chains only, in which each chain continues past its segment as
+ * soon as the next chain's list is published (one release per chain), so a
+ * long continuation does not wait for every other chain.  All modes give the
+ * same cuts. */
 int seqcdc_plan_set_mode(seqcdc_plan* plan, int mode);
 
 /* Overlapped batches (mode 0 only): the files of a seqcdc_chunk_batch call
@@ -125,9 +129,10 @@ int seqcdc_plan_stats(seqcdc_plan* plan, uint64_t* out3);
  * to every call).  seqcdc_plan_phase_ms waits for the plan's last timed call
  * and writes 4 durations in milliseconds.  Mode 0: the mark kernel (events
  * right before and after its launch), pass A (speculative chains),
- * pass B (continuations), stitch + compaction.  Mode 1: the pipeline kernel
- * (with the clearing before it), 0, the resume kernel (continuations the
- * pipeline left), stitch + compaction.  Overlapped batches: the marking of
+ * pass B (continuations), stitch + compaction.  Mode 1: the pipeline kernel,
+ * 0, the resume kernel (continuations the pipeline left), stitch +
+ * compaction.  Mode 2: the mark kernel, the chain pipeline kernel, the resume
+ * kernel, stitch + compaction.  Overlapped batches: the marking of
  * all groups on the caller's stream, then what each later step added after
  * the previous one ended (chains of the last group, the continuations, stitch
  * + compaction).  The values after the first are 0 when no stream had more

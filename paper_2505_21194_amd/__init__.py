@@ -168,7 +168,8 @@ def seqcdc_plan_set_tuning(plan, segment_bytes=0, mark_span_blocks=0, waves_per_
 
 
 def seqcdc_plan_set_mode(plan, mode):
-    """0: mark, pass A and pass B as separate launches (default); 1: the fused pipeline kernel."""
+    """0: mark, pass A and pass B as separate launches (default); 1: the fused pipeline kernel; 2: the mark kernel, then
+    a pipeline kernel of chains only."""
     _check(lib.seqcdc_plan_set_mode(plan, mode))
 
 

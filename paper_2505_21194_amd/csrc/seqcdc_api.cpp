@@ -283,7 +283,11 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   // Overlapped batches take the files largest first and cut them into groups
   // of about equal bytes; everything below (spans, chains) is numbered in
   // that order, so each group owns a contiguous range of spans and chains.
-  const bool fused = !mark_only && pl->mode_for(specs[0].p) == 1;
+  // resolve mode: 0 phased launches; 1 one pipeline kernel that marks and
+  // resolves; 2 the mark kernel, then a pipeline kernel of chains only
+  const int rmode = mark_only ? 0 : pl->mode_for(specs[0].p);
+  const bool fused = rmode == 1 || rmode == 2;
+  const bool premarked = rmode == 2;
   u64 total_n = 0;
   for (u32 f = 0; f < nfiles; f++) total_n += specs[f].n;
   u32 G = (mark_only || fused) ? 1 : pl->groups_for(nfiles, total_n);
@@ -393,6 +397,7 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
       const u64 nsp = (d.n + sb - 1) / sb;
       u64 next_span = 0;
       auto emit_spans = [&](u64 end_byte) {
+        if (premarked) return;
         const u64 upto = (std::min<u64>(end_byte, d.n) + sb - 1) / sb;
         for (; next_span < upto; next_span++) {
           span_pos[d.mark_span0 + next_span] = (u32)items.size();
@@ -525,14 +530,22 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
     pw.span_done = heads + 64;
     pw.chain_done = pw.span_done + spans;
     pw.resume = pw.chain_done + nchains + 64;
+    pw.premarked = premarked ? 1u : 0u;
     ws.stall = pw.resume + kStall;
     pl->last_resume = pw.resume;
     const u32 groups = std::max<u32>(1, pl->cus * waves / kWavesPerGroup);  // 4 independent waves each
-    HIP_TRY(timing_mark(pl, 0, st));
     HIP_TRY(launch_clear(heads, nflags, st));
-    HIP_TRY(launch_pipe(d_files, d_hint, ws, pw, groups, st));
-    HIP_TRY(timing_mark(pl, 1, st));
-    HIP_TRY(timing_mark(pl, 2, st));
+    HIP_TRY(timing_mark(pl, 0, st));
+    if (premarked) {
+      HIP_TRY(launch_mark(d_files, d_hint, 0, spans, U, st));
+      HIP_TRY(timing_mark(pl, 1, st));
+      HIP_TRY(launch_pipe(d_files, d_hint, ws, pw, std::max<u32>(1, std::min<u32>(groups, (nchains + 3) / 4)), st));
+      HIP_TRY(timing_mark(pl, 2, st));
+    } else {
+      HIP_TRY(launch_pipe(d_files, d_hint, ws, pw, groups, st));
+      HIP_TRY(timing_mark(pl, 1, st));
+      HIP_TRY(timing_mark(pl, 2, st));
+    }
     if (!multi.empty()) {
       HIP_TRY(launch_resume(d_files, ws, pw.resume, pl->cus, st));
       HIP_TRY(timing_mark(pl, 3, st));
@@ -769,7 +782,7 @@ int seqcdc_plan_set_tuning(seqcdc_plan* plan, uint64_t segment_bytes, uint32_t m
 
 int seqcdc_plan_set_mode(seqcdc_plan* plan, int mode) {
   if (!plan) return fail(SEQCDC_EINVAL, "plan is NULL");
-  if (mode != 0 && mode != 1) return fail(SEQCDC_EINVAL, "mode must be 0 (phased) or 1 (pipeline)");
+  if (mode < 0 || mode > 2) return fail(SEQCDC_EINVAL, "mode must be 0 (phased), 1 (pipeline) or 2 (chain pipeline)");
   Plan* pl = (Plan*)plan;
   std::lock_guard<std::mutex> g(pl->mu);
   pl->mode = mode;

@@ -93,8 +93,9 @@ extern "C" int seqcdc_autotune(seqcdc_plan* plan, const void* d_sample, uint64_t
     for (u32 w : {8u, 12u, 20u})
       if ((rc = trial(m, s, w))) break;
   }
-  if (!rc) {  // the fused pipeline at the best shape so far
-    pl->mode = 1;
+  for (int m : {1, 2}) {  // the pipeline modes at the best shape so far
+    if (rc) break;
+    pl->mode = m;
     rc = trial(best.seg_mult, best.span_blocks, best.waves_per_cu);
   }
   pl->mode = saved_mode;

@@ -79,6 +79,7 @@ struct PipeWs {
   u32* span_done;        // per global span: bits written and released
   u32* chain_done;       // per global chain: pass A list published
   u32* resume;           // resume list and counters, indexed by the constants below
+  u32 premarked;         // every span was marked by an earlier kernel: the list holds chains only
 };
 
 constexpr u32 kResumeCount = 0;  // continuations to resume

@@ -158,7 +158,7 @@ __device__ __forceinline__ void count_timeout(const PipeWs& pw) {
 // boundary at or before the first byte it reads).
 __device__ __forceinline__ void chain_pipe(Chain& ch, const FileDesc& F, const PipeWs* pw, u32 ready_blk) {
   ch.pw = pw;
-  ch.ready_blk = ready_blk < ch.nblocks ? ready_blk : ch.nblocks;
+  ch.ready_blk = (pw->premarked || ready_blk >= ch.nblocks) ? ch.nblocks : ready_blk;
   ch.span0 = (u32)F.mark_span0;
 }
 

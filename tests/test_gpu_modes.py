@@ -34,29 +34,31 @@ def P(mode=0, sl=5, mn=4096, mx=16384, trig=50, skip=256):
 
 @pytest.mark.parametrize("seg_kib", [64, 1024])
 @pytest.mark.parametrize("gen", ["uniform", "mixed"])
-def test_fused_mode_plain(env, seg_kib, gen):
+@pytest.mark.parametrize("pmode", [1, 2])
+def test_fused_mode_plain(env, seg_kib, gen, pmode):
     torch, seq = env
     data = (synth.uniform if gen == "uniform" else synth.mixed)(24 << 20, seed=seg_kib)
     want = oracle.chunk(data, **P())
     d = torch.from_numpy(data).cuda()
     outs = {}
-    for mode in (1, 0):
+    for mode in (pmode, 0):
         plan = seq.seqcdc_plan_create()
         try:
             seq.seqcdc_plan_set_tuning(plan, segment_bytes=seg_kib << 10)
             seq.seqcdc_plan_set_mode(plan, mode)
             _say("plain", gen, "seg", seg_kib, "KiB mode", mode)
             outs[mode] = seq.chunk(d, P(), plan=plan).cpu().numpy().astype(np.uint64)
-            if mode == 1:
+            if mode != 0:
                 resumed, timeouts, stall = seq.seqcdc_plan_stats(plan)
                 assert timeouts == 0 and stall == 0
         finally:
             seq.seqcdc_plan_destroy(plan)
-    assert np.array_equal(outs[1], want)
+    assert np.array_equal(outs[pmode], want)
     assert np.array_equal(outs[0], want)
 
 
-def test_fused_mode_batch(env):
+@pytest.mark.parametrize("pmode", [1, 2])
+def test_fused_mode_batch(env, pmode):
     torch, seq = env
     rng = np.random.default_rng(9)
     sizes = [int(x) for x in rng.integers(0, 2 << 20, 60)] + [0, 1, 4097, 6 << 20]
@@ -67,8 +69,8 @@ def test_fused_mode_batch(env):
     plan = seq.seqcdc_plan_create()
     try:
         seq.seqcdc_plan_set_tuning(plan, segment_bytes=128 << 10)
-        seq.seqcdc_plan_set_mode(plan, 1)
-        _say("fused batch", len(sizes), "files")
+        seq.seqcdc_plan_set_mode(plan, pmode)
+        _say("pipeline mode", pmode, "batch", len(sizes), "files")
         outs = seq.chunk_batch(tens, params, params_index=pidx, plan=plan)
         assert seq.seqcdc_plan_stats(plan)[1:] == (0, 0)
     finally:
@@ -145,7 +147,7 @@ def test_overlapped_batch(env, groups):
         seq.seqcdc_plan_destroy(plan)
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_many_small_files(env, mode):
     """Thousands of tiny files, many per 64 mark spans (the span -> file lookup), plus a few large ones."""
     torch, seq = env
@@ -169,7 +171,7 @@ def test_many_small_files(env, mode):
         assert np.array_equal(o.cpu().numpy().astype(np.uint64), oracle.chunk(x, **p)), i
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_prepared_batch_graph_replays(env, mode):
     """A prepared (hipGraph-captured) batch: each replay, with new input contents and eager work in between,
     equals the oracle."""
