@@ -107,15 +107,19 @@ int seqcdc_plan_get_tuning(seqcdc_plan* plan, uint64_t n, const seqcdc_params* p
 int seqcdc_plan_set_mode(seqcdc_plan* plan, int mode);
 
 /* Overlapped batches (mode 0 only): the files of a seqcdc_chunk_batch call
- * are taken largest first and cut into `groups` groups of about equal bytes.
- * The caller's stream marks one group after the other while two side streams
- * of the plan (default priority) run the chains of each group as soon as its
- * marks are done, the continuations of the first group (the largest files)
- * as soon as its chains are done, then the remaining continuations, stitch
- * and compaction; the caller's stream waits for them before the call's work
- * counts as done.  0 = default (off: on MI355X the chains slow the mark
- * kernel down about as much as the overlap gains), 1 = off, up to 8.  Results
- * do not depend on it. */
+ * are taken largest first and cut into groups.  The caller's stream marks one
+ * group after the other while two side streams of the plan (default
+ * priority) run the chains of each group as soon as its marks are done, the
+ * continuations of the first group as soon as its chains are done, then the
+ * remaining continuations, stitch and compaction; the caller's stream waits
+ * for them before the call's work counts as done.  0 = default (off: back
+ * to back, or with several serving passes in flight, the side streams cost
+ * more than the overlap gains on MI355X); 1 = off; 2 = two groups, the files
+ * with more than one segment (whose continuations are the long part of
+ * resolve) and the others (equal byte shares if the batch has one kind
+ * only), which shortens a single synchronous call by about 5 %; up to 8 =
+ * groups of about equal bytes.  Results do not depend on it.  Prepared
+ * batches (below) do not overlap. */
 int seqcdc_plan_set_overlap(seqcdc_plan* plan, uint32_t groups);
 
 /* Diagnostics of the plan's last pipeline-mode call (waits for it): out3[0] =

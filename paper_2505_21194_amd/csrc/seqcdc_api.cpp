@@ -188,8 +188,9 @@ u32 Plan::waves_for(const seqcdc_params* p) const {
   return 8;
 }
 
-// Overlapped batches are off unless asked for: on MI355X the chains that run
-// beside the mark kernel slow it down about as much as they gain.
+// Overlapped batches are off unless asked for: measured back to back, and
+// with several serving passes in flight, the side streams cost more than the
+// overlap gains (a single synchronous call does gain from two groups).
 u32 Plan::groups_for(u32 nfiles, u64 total) const {
   (void)total;
   if (overlap) return std::min<u32>(overlap, std::min<u32>(nfiles, kMaxGroups));
@@ -358,9 +359,19 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
       }
     }
   }
-  // group g holds files [gfile[g], gfile[g+1]); empty groups are dropped
+  // group g holds files [gfile[g], gfile[g+1]); empty groups are dropped.
+  // Two groups: the files with more than one segment (their continuations
+  // are the long part of resolve) and the others.  More: equal byte shares.
   std::vector<u32> gfile{0};
-  if (G > 1) {
+  u32 first_single = nfiles;
+  for (u32 f = 0; f < nfiles; f++)
+    if (fd[f].nseg == 1) {
+      first_single = f;
+      break;
+    }
+  if (G == 2 && first_single > 0 && first_single < nfiles) {
+    gfile.push_back(first_single);
+  } else if (G > 1) {
     u64 acc = 0;
     for (u32 f = 0; f < nfiles && gfile.size() < G; f++) {
       acc += fd[f].n;
