@@ -146,7 +146,7 @@ def batched(seq, torch, stream, plan, steps, warmup, dev, tune):
             "tuning": tuning}
 
 
-def serving(seq, torch, dev):
+def serving(seq, torch, dev, streams=4, max_batch=64):
     """Poisson request stream through the serving loop; returns latency percentiles per offered load."""
     import synth
     vers = synth.snapshot_series(256 << 20, 3, seed=11, nedits=200, maxlen=4096)
@@ -163,7 +163,7 @@ def serving(seq, torch, dev):
         reqs.append((dvers[v].data_ptr() + off, n, i % 2))
     total = sum(r[1] for r in reqs)
     arr = (seq.seqcdc_params * 2)(*params)
-    cfg = seq.seqcdc_server_config(0, 4 << 30, 256, 4, 64, 2, arr)
+    cfg = seq.seqcdc_server_config(0, 4 << 30, 256, streams, max_batch, 2, arr)
     h = ctypes.c_void_p()
     if seq.lib.seqcdc_server_create(ctypes.byref(cfg), ctypes.byref(h)):
         raise RuntimeError(seq.last_error())
