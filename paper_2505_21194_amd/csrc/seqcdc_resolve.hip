@@ -1,6 +1,5 @@
 // SeqCDC resolve step on CDNA4 (gfx950): the exact sequential state machine
-// of the paper run over the mark bits, fused with marking in one persistent
-// pipeline kernel.
+// of the paper run over the mark bits, speculatively per segment.
 //
 // From a cut at c (Sec. III-B) scanning starts at s = c + min - SeqLength;
 // the chunk ends one byte past the first run end E at or after s+SeqLength-1
@@ -15,10 +14,13 @@
 // depends only on the cut's position, so once two chains share a cut they
 // agree from then on.  Pass B continues each chain past its segment until one
 // of its cuts belongs to the chain that owns that position; the stitch then
-// keeps the exact pieces and the compaction writes them out.  Every
-// dependency between workgroups is a kernel boundary: mark, pass A, pass B,
-// stitch and compaction are separate launches, and the only shared state
-// inside a launch is its atomic work counter.
+// keeps the exact pieces and the compaction writes them out.  In the default
+// (phased) mode every dependency between workgroups is a kernel boundary:
+// mark, pass A, pass B, stitch and compaction are separate launches, and the
+// only shared state inside a launch is its atomic work counter.  The pipeline
+// modes hand out marking and chains (mode 1), or chains only (mode 2), from
+// one ordered list inside a persistent kernel, ordered by agent-scope flags
+// with bounded waits; what a wait cannot get is finished by a resume kernel.
 //
 // A chain is one wave, and the waves of a workgroup take chains
 // independently.  Its state is wave-uniform (scalar registers); the lanes
