@@ -13,6 +13,10 @@ Reported beside it (not the headline value):
   serving: Poisson arrivals of requests (log-normal sizes, median 1 MiB, sigma 1.5, clamped 1 KiB..256 MiB) that
            are slices of a device-resident snapshot series, 8 and 32 KiB averages mixed; offered load at 10/40/80 %
            of the server's saturated rate; p50/p99 latency and GB/s, against the plain per-request path.
+  sweep:   the other plain variants (both modes at 8 / 16 / 32 KiB averages and SeqLength 6 on the 1 GiB stream;
+           8 MiB of uniform bytes at 8 KiB with max 16 and 64 KiB).
+Settings (segment length, mark span, chain occupancy, resolve mode) come from the library's autotuner, run
+untimed on each workload first (--no-tune: defaults).
 value = plain input bytes per second (GB/s = 1e9 B/s).
 """
 import argparse
@@ -38,6 +42,7 @@ def parse():
     ap.add_argument("--size-mib", type=int, default=1024)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the other plain variants")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the library's autotuner (default settings)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="oracle work to time on the host")
@@ -73,7 +78,7 @@ def mark_roofline(n, kernel_ms, traffic_json):
             "kernel_ms": round(ms, 4), "alg_bytes_per_launch": alg}
 
 
-def batched(seq, torch, stream, plan, steps, warmup, dev, tune):
+def batched(seq, torch, stream, plan, steps, warmup, dev, tune, cpu_context=True):
     import synth
     nfiles = 4096
     sizes = synth.lognormal_sizes(nfiles, 256 * 1024, 1.5, 4096, 64 << 20, seed=4).astype(np.int64)
@@ -112,6 +117,24 @@ def batched(seq, torch, stream, plan, steps, warmup, dev, tune):
     torch.cuda.synchronize()
     bdt = (time.perf_counter() - t0) / steps
     counts = bcounts.cpu().numpy()
+    # context: the oracle over the same files on the host's cores, one file per thread at a time
+    cpu_all = None
+    if cpu_context:
+        import oracle
+        from concurrent.futures import ThreadPoolExecutor
+        host = [buf[int(offs[f]):int(offs[f + 1])].cpu().numpy() for f in range(nfiles)]
+        cores = min(16, len(os.sched_getaffinity(0)))
+        kw = dict(mode=pb.mode, seq_length=pb.seq_length, min_size=pb.min_size, max_size=pb.max_size,
+                  skip_trigger=pb.skip_trigger, skip_size=pb.skip_size)
+        order = sorted(range(nfiles), key=lambda f: -host[f].size)
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(cores) as ex:
+            cpu_counts = dict(zip(order, ex.map(lambda f: oracle.chunk(host[f], **kw).size, order)))
+        cdt = time.perf_counter() - t0
+        cpu_all = {"value": round(total / cdt / 1e9, 2), "unit": "GB/s", "cores": cores, "kind": "oracle",
+                   "sample": "the whole batch, one file per thread (context, not the baseline)",
+                   "counts_match": bool(all(cpu_counts[f] == int(counts[f]) for f in range(nfiles)))}
+        del host
     # the same batch prepared once and replayed as a hipGraph
     gb = seq.seqcdc_batch_prepare(ftab, [pb], bcuts.data_ptr(), otab, bcounts.data_ptr(), settings=plan)
     try:
@@ -143,7 +166,7 @@ def batched(seq, torch, stream, plan, steps, warmup, dev, tune):
             "graph_counts_match": graph_same,
             "per_file_launch_GBps": round(total / pdt / 1e9, 2), "speedup_vs_per_file": round(pdt / bdt, 2),
             "params": "avg 16 KiB: SeqLength 5, SkipTrigger 50, SkipSize 512, min 8 KiB, max 32 KiB",
-            "tuning": tuning}
+            "tuning": tuning, "cpu_all_cores": cpu_all}
 
 
 def serving(seq, torch, dev, streams=4, max_batch=64):
@@ -220,6 +243,50 @@ def serving(seq, torch, dev, streams=4, max_batch=64):
     return {"requests": nreq, "bytes": total, "saturated": sat, "loads": loads,
             "plain_per_request": {"GBps": round(total / dt / 1e9, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
                                   "p99_ms": round(float(np.percentile(lat, 99)), 3)}}
+
+
+def sweep(seq, torch, stream, d, steps, tune):
+    """GPU rate of the other plain variants: the 1 GiB mixed stream in both modes at 8 / 16 / 32 KiB averages
+    (Table I) and at SeqLength 6, and the 8 MiB uniform buffer of seed 0 at 8 KiB with max 16 and 64 KiB."""
+    import synth
+    out = []
+    small = torch.from_numpy(synth.uniform(8 << 20, seed=0)).to(d.device)
+    cases = []
+    for avg in (8, 16, 32):
+        for mode in (0, 1):
+            p = seq.seqcdc_params_for_avg(avg << 10)
+            p.mode = mode
+            cases.append(("1 GiB mixed, %s, avg %d KiB" % ("increasing" if mode == 0 else "decreasing", avg), d, p))
+    p6 = seq.seqcdc_params_for_avg(8192)
+    p6.seq_length = 6
+    cases.append(("1 GiB mixed, increasing, avg 8 KiB parameters with SeqLength 6", d, p6))
+    cases.append(("8 MiB uniform (seed 0), increasing, avg 8 KiB, max 16 KiB", small, seq.seqcdc_params_for_avg(8192)))
+    p64 = seq.seqcdc_params_for_avg(8192)
+    p64.max_size = 65536
+    cases.append(("8 MiB uniform (seed 0), increasing, avg 8 KiB, max 64 KiB", small, p64))
+    plan = seq.seqcdc_plan_create()
+    try:
+        for name, t, p in cases:
+            n = t.numel()
+            cap = seq.seqcdc_max_cuts(n, p)
+            cuts = torch.empty(cap, dtype=torch.int64, device=t.device)
+            if tune and n >= (64 << 20):
+                seq.seqcdc_autotune(plan, t.data_ptr(), n, p, stream=stream)
+            for _ in range(2):
+                cnt = seq.seqcdc_chunk(t.data_ptr(), n, p, cuts.data_ptr(), cap, stream=stream, plan=plan)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                cnt = seq.seqcdc_chunk(t.data_ptr(), n, p, cuts.data_ptr(), cap, stream=stream, plan=plan)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            seg, span, waves = seq.seqcdc_plan_get_tuning(plan, n, p)
+            out.append({"workload": name, "ms": round(dt * 1e3, 4), "GBps": round(n / dt / 1e9, 1), "cuts": cnt,
+                        "tuning": {"segment_bytes": seg, "mark_span_blocks": span, "waves_per_cu": waves}})
+            del cuts
+    finally:
+        seq.seqcdc_plan_destroy(plan)
+    return out
 
 
 def cpu_baseline(host, p, seconds):
@@ -312,11 +379,15 @@ def main():
 
     extra = {"phases_ms": phases}
     if not args.no_batch:
-        extra["batched"] = batched(seq, torch, stream, plan, args.steps, args.warmup, dev, not args.no_tune)
+        extra["batched"] = batched(seq, torch, stream, plan, args.steps, args.warmup, dev, not args.no_tune,
+                                   not args.no_cpu)
         log("batched: %s" % extra["batched"])
     if not args.no_serve:
         extra["serving"] = serving(seq, torch, dev)
         log("serving: %s" % extra["serving"])
+    if not args.no_sweep:  # last: its autotuning sets the process-wide choices of more parameter classes
+        extra["sweep"] = sweep(seq, torch, stream, d, args.steps, not args.no_tune)
+        log("sweep: %s" % extra["sweep"])
 
     cpu = None
     if not args.no_cpu:

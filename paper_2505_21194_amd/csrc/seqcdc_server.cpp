@@ -218,6 +218,11 @@ int seqcdc_server_create(const seqcdc_server_config* cfg, seqcdc_server** out) {
   for (u32 i = 0; i < cfg->streams; i++) {
     Pass* ps = new Pass();
     int rc = plan_init(&ps->plan, dev);
+    // Passes are batches of many requests, mostly small: always the phased
+    // launches (a pipeline mode tuned on one long stream would serialise them)
+    // and no overlapped groups (each pass already runs beside the others).
+    ps->plan.mode = 0;
+    ps->plan.overlap = 1;
     hipError_t e = hipSuccess;
     if (!rc) e = hipStreamCreateWithFlags(&ps->stream, hipStreamNonBlocking);
     if (!rc && e == hipSuccess) e = hipEventCreateWithFlags(&ps->done, hipEventDisableTiming);
