@@ -215,14 +215,14 @@ int plan_init(Plan* pl, int device) {
   pl->cus = (u32)prop.multiProcessorCount;
   pl->arch = std::string(prop.gcnArchName);
   HIP_TRY(hipEventCreateWithFlags(&pl->call_done, hipEventDisableTiming));
-  for (hipEvent_t& e : pl->upload_done) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&pl->upload_done, hipEventDisableTiming));
   return SEQCDC_OK;
 }
 
 void plan_free(Plan* pl) {
   if (pl->pending) (void)hipEventSynchronize(pl->call_done);
   for (DevBuf* b : {&pl->eo, &pl->esum, &pl->list, &pl->cont, &pl->chains, &pl->tables, &pl->flags, &pl->misc}) b->release();
-  for (HostBuf& b : pl->staging) b.release();
+  pl->staging.release();
   pl->readback.release();
   for (hipEvent_t& e : pl->tev)
     if (e) (void)hipEventDestroy(e);
@@ -233,8 +233,7 @@ void plan_free(Plan* pl) {
   for (hipStream_t s : pl->side)
     if (s) (void)hipStreamDestroy(s);
   if (pl->call_done) (void)hipEventDestroy(pl->call_done);
-  for (hipEvent_t e : pl->upload_done)
-    if (e) (void)hipEventDestroy(e);
+  if (pl->upload_done) (void)hipEventDestroy(pl->upload_done);
 }
 
 template <class T>
@@ -457,15 +456,12 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   }
 
   // ---- stage tables (pinned) and upload
-  // a capture lays out into the buffer of the identical eager call before it
-  // (already sized: nothing may be allocated while a stream captures)
-  const u32 sg = pl->capturing ? (pl->stage ^ 1u) : pl->stage;
-  if (pl->upload_pending[sg] && !pl->capturing) {
-    HIP_TRY(hipEventSynchronize(pl->upload_done[sg]));
-    pl->upload_pending[sg] = false;
+  if (pl->upload_pending && !pl->capturing) {
+    HIP_TRY(hipEventSynchronize(pl->upload_done));
+    pl->upload_pending = false;
   }
-  if ((rc = pl->staging[sg].reserve(table_bytes))) return rc;
-  char* h = (char*)pl->staging[sg].p;
+  if ((rc = pl->staging.reserve(table_bytes))) return rc;
+  char* h = (char*)pl->staging.p;
   char* dbase = (char*)pl->tables.p;
   char* cur = h;
   FileDesc* h_files = carve<FileDesc>(cur, nfiles);
@@ -501,9 +497,8 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   auto dev = [&](void* hp) { return (void*)(dbase + ((char*)hp - h)); };
   if (!pl->capturing) {  // a capture replays tables uploaded by an identical eager call
     HIP_TRY(hipMemcpyAsync(dbase, h, used, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipEventRecord(pl->upload_done[sg], st));
-    pl->upload_pending[sg] = true;
-    pl->stage = sg ^ 1u;
+    HIP_TRY(hipEventRecord(pl->upload_done, st));
+    pl->upload_pending = true;
   }
 
   const FileDesc* d_files = (const FileDesc*)dev(h_files);
@@ -693,7 +688,7 @@ int chunk_plan(Plan* pl, const void* d_stream, u64 n, const seqcdc_params* p, u6
   HIP_TRY(hipMemcpyAsync(pl->readback.p, s.out_count, 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   pl->pending = false;
-  pl->uploads_done();
+  pl->upload_pending = false;
   *h_count = *(u64*)pl->readback.p;
   if (*h_count == ~0ull) return fail(SEQCDC_EHIP, "internal error: a resolve chain could not finish");
   if (*h_count > cap) return fail(SEQCDC_ECAPACITY, "need %llu cuts, capacity %llu", (unsigned long long)*h_count,

@@ -75,7 +75,7 @@ static int prepare(Plan* settings, const seqcdc_file* files, u32 nfiles, const s
     return rc;
   }
   pl.pending = false;
-  pl.uploads_done();
+  pl.upload_pending = false;
   // The same call again under stream capture: the layout is identical, so no
   // buffer grows and the tables already on the device are the ones it uses.
   if (!hip(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture")) {

@@ -53,13 +53,9 @@ struct Plan {
   std::string arch;
   std::mutex mu;
   DevBuf eo, esum, list, cont, chains, tables, flags, misc;
-  // pinned staging for the tables, two buffers used in turn, so that laying
-  // out a call only waits for the upload of the call before the previous one
-  HostBuf staging[2], readback;
-  hipEvent_t call_done = nullptr, upload_done[2] = {nullptr, nullptr};
-  bool pending = false, upload_pending[2] = {false, false};
-  u32 stage = 0;
-  void uploads_done() { upload_pending[0] = upload_pending[1] = false; }
+  HostBuf staging, readback;
+  hipEvent_t call_done = nullptr, upload_done = nullptr;
+  bool pending = false, upload_pending = false;
   hipStream_t last_stream = nullptr;
   u32 last_nchains = 0, last_multi = 0;
   u64 seg_override = 0;

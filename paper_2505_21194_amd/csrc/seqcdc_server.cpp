@@ -121,7 +121,7 @@ static void finish_pass(Server* s, Pass* ps, int status) {
     s->reqs_inflight--;
   }
   ps->plan.pending = false;
-  ps->plan.uploads_done();
+  ps->plan.upload_pending = false;
   ps->reqs.clear();
   ps->busy = false;
   s->cv_done.notify_all();
