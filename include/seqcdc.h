@@ -238,8 +238,9 @@ int seqcdc_dedup_stats(const uint8_t* const* h_buffers, const uint64_t* const* h
  * memory budget and a ring slot is free, launches each admitted group as one
  * batched pass on one of `streams` HIP streams (groups overlap on the GPU),
  * and publishes each request's cuts and latency when its pass completes.
- * Passes use the phased resolve launches without overlapped groups; segment
- * length, mark span and occupancy follow the autotuner's choices, if any. 
+ * Passes use the phased resolve launches without overlapped groups and 8
+ * chain waves per compute unit; segment length and mark span follow the
+ * autotuner's choices, if any. 
  * ------------------------------------------------------------------- */
 typedef struct {
   int device;                /* -1 = current */

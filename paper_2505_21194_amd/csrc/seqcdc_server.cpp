@@ -26,6 +26,8 @@
 
 namespace seqcdc {
 
+constexpr u32 kServerWaves = 8;  // chain waves per CU of each serving pass
+
 using Clock = std::chrono::steady_clock;
 
 static double ms_between(Clock::time_point a, Clock::time_point b) {
@@ -218,11 +220,14 @@ int seqcdc_server_create(const seqcdc_server_config* cfg, seqcdc_server** out) {
   for (u32 i = 0; i < cfg->streams; i++) {
     Pass* ps = new Pass();
     int rc = plan_init(&ps->plan, dev);
-    // Passes are batches of many requests, mostly small: always the phased
-    // launches (a pipeline mode tuned on one long stream would serialise them)
-    // and no overlapped groups (each pass already runs beside the others).
+    // Passes are batches of many requests, mostly small, several in flight:
+    // always the phased launches (a pipeline mode tuned on one long stream
+    // would serialise them), no overlapped groups, and a fixed chain
+    // occupancy, so that one pass's persistent chain kernels leave room (LDS,
+    // wave slots) for the others'.
     ps->plan.mode = 0;
     ps->plan.overlap = 1;
+    ps->plan.waves_override = kServerWaves;
     hipError_t e = hipSuccess;
     if (!rc) e = hipStreamCreateWithFlags(&ps->stream, hipStreamNonBlocking);
     if (!rc && e == hipSuccess) e = hipEventCreateWithFlags(&ps->done, hipEventDisableTiming);
