@@ -122,6 +122,14 @@ int seqcdc_plan_set_mode(seqcdc_plan* plan, int mode);
  * batches (below) do not overlap. */
 int seqcdc_plan_set_overlap(seqcdc_plan* plan, uint32_t groups);
 
+/* Bound of the waits inside the pipeline modes (1 and 2): a wave waiting for
+ * a flag (marked span, published chain list) sleeps briefly up to `rounds`
+ * times, then falls back (a continuation is left to the resume kernel; a
+ * chain that cannot get its bits stops, and the call reports an error).
+ * 0 = default (2^20 rounds, never reached in practice).  Small values force
+ * the fallbacks, for testing failure handling. */
+int seqcdc_plan_set_wait_limit(seqcdc_plan* plan, uint32_t rounds);
+
 /* Diagnostics of the plan's last pipeline-mode call (waits for it): out3[0] =
  * continuations the pipeline kernel left to the resume kernel (they reached
  * work not handed out yet), out3[1] = bounded waits that ran out (expected

@@ -68,6 +68,7 @@ _SIGS = {
     "seqcdc_plan_set_tuning": ([_p, _u64, _u32, _u32], ctypes.c_int),
     "seqcdc_plan_set_mode": ([_p, ctypes.c_int], ctypes.c_int),
     "seqcdc_plan_set_overlap": ([_p, _u32], ctypes.c_int),
+    "seqcdc_plan_set_wait_limit": ([_p, _u32], ctypes.c_int),
     "seqcdc_plan_stats": ([_p, ctypes.POINTER(_u64)], ctypes.c_int),
     "seqcdc_plan_set_timing": ([_p, ctypes.c_int], ctypes.c_int),
     "seqcdc_plan_phase_ms": ([_p, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
@@ -176,6 +177,11 @@ def seqcdc_plan_set_mode(plan, mode):
 def seqcdc_plan_set_overlap(plan, groups):
     """Overlapped batches: 0 = default, 1 = off, 2..8 file groups whose marking overlaps earlier groups' chains."""
     _check(lib.seqcdc_plan_set_overlap(plan, groups))
+
+
+def seqcdc_plan_set_wait_limit(plan, rounds):
+    """Bound of the pipeline modes' waits (0 = default); small values force their fallbacks."""
+    _check(lib.seqcdc_plan_set_wait_limit(plan, rounds))
 
 
 def seqcdc_plan_stats(plan):

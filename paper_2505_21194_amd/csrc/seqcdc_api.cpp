@@ -542,6 +542,7 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
     pw.chain_done = pw.span_done + spans;
     pw.resume = pw.chain_done + nchains + 64;
     pw.premarked = premarked ? 1u : 0u;
+    pw.wait_rounds = pl->wait_rounds ? pl->wait_rounds : kDefaultWaitRounds;
     ws.stall = pw.resume + kStall;
     pl->last_resume = pw.resume;
     const u32 groups = std::max<u32>(1, pl->cus * waves / kWavesPerGroup);  // 4 independent waves each
@@ -806,6 +807,14 @@ int seqcdc_plan_set_overlap(seqcdc_plan* plan, uint32_t groups) {
   Plan* pl = (Plan*)plan;
   std::lock_guard<std::mutex> g(pl->mu);
   pl->overlap = groups;
+  return SEQCDC_OK;
+}
+
+int seqcdc_plan_set_wait_limit(seqcdc_plan* plan, uint32_t rounds) {
+  if (!plan) return fail(SEQCDC_EINVAL, "plan is NULL");
+  Plan* pl = (Plan*)plan;
+  std::lock_guard<std::mutex> g(pl->mu);
+  pl->wait_rounds = rounds;
   return SEQCDC_OK;
 }
 

@@ -56,6 +56,7 @@ static int prepare(Plan* settings, const seqcdc_file* files, u32 nfiles, const s
     pl.seg_override = settings->seg_override;
     pl.span_override = settings->span_override;
     pl.waves_override = settings->waves_override;
+    pl.wait_rounds = settings->wait_rounds;
     pl.mode = settings->mode_for(params);
   }
   pl.overlap = 1;  // one stream: the graph is a single chain of kernels

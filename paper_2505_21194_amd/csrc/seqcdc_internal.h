@@ -80,6 +80,7 @@ struct PipeWs {
   u32* chain_done;       // per global chain: pass A list published
   u32* resume;           // resume list and counters, indexed by the constants below
   u32 premarked;         // every span was marked by an earlier kernel: the list holds chains only
+  u32 wait_rounds;       // bound of every wait on a flag (rounds of a short sleep)
 };
 
 constexpr u32 kResumeCount = 0;  // continuations to resume

@@ -131,8 +131,6 @@ __device__ __forceinline__ void chain_init(Chain& ch, const FileDesc& F, SEQCDC_
 // wait that runs out (never expected) is counted and the waiter falls back.
 // ---------------------------------------------------------------------------
 
-constexpr u32 kWaitRounds = 1u << 20;
-
 // Every lane's earlier stores become visible to an acquirer of *flag.
 __device__ __forceinline__ void publish(u32* flag) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -187,7 +185,7 @@ __device__ bool make_ready(Chain& ch, u32 need_blk) {
       rounds = 0;
     } else {
       if (!handed_out(pw, pw.span_pos[ch.span0 + s])) return false;
-      if (++rounds > kWaitRounds) {
+      if (++rounds > pw.wait_rounds) {
         count_timeout(pw);
         return false;
       }
@@ -461,7 +459,7 @@ __device__ __forceinline__ bool need_pass_a(const PipeWs* pw, u32 chain) {
     if (!handed_out(*pw, pw->chain_pos[chain])) return false;
     u32 rounds = 0;
     while (!is_set(&pw->chain_done[chain])) {
-      if (++rounds > kWaitRounds) {
+      if (++rounds > pw->wait_rounds) {
         count_timeout(*pw);
         return false;
       }

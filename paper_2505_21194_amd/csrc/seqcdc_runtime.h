@@ -13,6 +13,7 @@ namespace seqcdc {
 
 constexpr u64 kMaxSegments = 65536;  // per stream
 constexpr u32 kMaxGroups = 8;        // file groups of an overlapped batch
+constexpr u32 kDefaultWaitRounds = 1u << 20;  // pipeline waits: rounds of a short sleep before falling back
 constexpr u64 kMaxStream = 1ull << 38;  // 256 GiB: group and sub-window indices stay 32-bit
 
 struct DevBuf {
@@ -70,6 +71,7 @@ struct Plan {
   // later groups run on the caller's stream while side[0] runs the chains of
   // earlier ones and side[1] their continuations
   u32 overlap = 0;  // groups (0: default, 1: off)
+  u32 wait_rounds = 0;  // bound of the pipeline modes' waits (0: kDefaultWaitRounds)
   hipStream_t side[2] = {nullptr, nullptr};
   hipEvent_t ev_mark[kMaxGroups] = {};
   hipEvent_t ev_chain_first = nullptr, ev_chain_last = nullptr, ev_join = nullptr;

@@ -218,3 +218,53 @@ def test_prepared_batch_graph_replays(env, mode):
         seq.seqcdc_batch_destroy(batch)
         seq.seqcdc_plan_destroy(settings)
         seq.seqcdc_plan_destroy(other)
+
+
+@pytest.mark.parametrize("pmode", [1, 2])
+def test_pipeline_wait_limit_fallbacks(env, pmode):
+    """Failure handling forced from the host: with the pipeline modes' bounded waits cut to one round, waits run
+    out.  Mode 2 leaves such continuations to the resume kernel and must still give exact cuts; mode 1 may also
+    stop a chain that cannot get its bits, and must then report it (count ~0, stall flag), never wrong cuts.
+    Every kernel exits normally either way."""
+    torch, seq = env
+    rng = np.random.default_rng(300 + pmode)
+    sizes = [int(x) for x in rng.integers(0, 3 << 20, 30)] + [6 << 20, 0, 1]
+    p = P()
+    datas = [synth.mixed(s, seed=7000 + i) for i, s in enumerate(sizes)]
+    tens = [torch.from_numpy(x).cuda() if x.size else torch.zeros(0, dtype=torch.uint8, device="cuda") for x in datas]
+    ps = seq.make_params(**p)
+    offs = [0]
+    for s in sizes:
+        offs.append(offs[-1] + max(seq.seqcdc_max_cuts(s, ps), 1))
+    cuts = torch.zeros(offs[-1], dtype=torch.int64, device="cuda")
+    counts = torch.zeros(len(sizes), dtype=torch.int64, device="cuda")
+    plan = seq.seqcdc_plan_create()
+    try:
+        seq.seqcdc_plan_set_tuning(plan, segment_bytes=128 << 10)
+        seq.seqcdc_plan_set_mode(plan, pmode)
+        seq.seqcdc_plan_set_wait_limit(plan, 1)
+        _say("pipeline mode", pmode, "with one-round waits")
+        seq.seqcdc_chunk_batch([(t.data_ptr(), t.numel(), 0) for t in tens], [ps], cuts.data_ptr(), offs,
+                               counts.data_ptr(), plan=plan)
+        torch.cuda.synchronize()
+        resumed, timeouts, stall = seq.seqcdc_plan_stats(plan)
+        cnt = counts.cpu().numpy().astype(np.uint64)
+        allc = cuts.cpu().numpy().astype(np.uint64)
+        stopped = 0
+        for i, x in enumerate(datas):
+            if cnt[i] == np.uint64(0xFFFFFFFFFFFFFFFF):
+                stopped += 1
+                continue
+            assert np.array_equal(allc[offs[i]:offs[i] + int(cnt[i])], oracle.chunk(x, **p)), i
+        if pmode == 2:
+            assert stopped == 0 and stall == 0
+        else:
+            assert (stopped > 0) == (stall == 1)
+        # the same plan with the default bound again: everything exact
+        seq.seqcdc_plan_set_wait_limit(plan, 0)
+        outs = seq.chunk_batch(tens, [p], plan=plan)
+        for i, (x, o) in enumerate(zip(datas, outs)):
+            assert np.array_equal(o.cpu().numpy().astype(np.uint64), oracle.chunk(x, **p)), i
+        assert seq.seqcdc_plan_stats(plan)[1:] == (0, 0)
+    finally:
+        seq.seqcdc_plan_destroy(plan)
