@@ -34,6 +34,7 @@
 #include <hip/hip_runtime.h>
 
 #include "seqcdc_mark.h"
+#include "seqcdc_workspace.h"
 
 namespace seqcdc {
 

@@ -8,6 +8,7 @@
 
 #include "../../include/seqcdc.h"
 #include "seqcdc_internal.h"
+#include "seqcdc_workspace.h"
 
 namespace seqcdc {
 
