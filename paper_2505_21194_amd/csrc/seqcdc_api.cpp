@@ -520,7 +520,7 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   ws.cont_cnt = carve<u32>(cc, nchains);
   ws.active = carve<u32>(cc, nchains);
   ws.entry_idx = carve<i32>(cc, nchains);
-  ws.jumps = carve<u32>(cc, nchains);
+  ws.jumps = (u32*)carve<u64>(cc, nchains);
   ws.out_off = carve<u64>(cc, nchains);
   ws.covered = (u32*)carve<u64>(cc, nchains);
 

@@ -517,6 +517,17 @@ __device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ fi
   i32 conv_idx = -1;
   bool stopped = false;
   SEQCDC_GLOBAL u64* cont = as_global(ws.cont + ws.cont_off[chain]);
+  // Entries [from, cc) wait in the lanes (entry i in lane i % 64) and are
+  // stored 64 at a time: a store per cut would make every later wait for a
+  // window DMA wait for that store too (one counter covers loads and stores).
+  const u32 lane = lane_id();
+  u32 from = cc;
+  u64 buf = 0;
+  auto flush = [&]() {
+    const u32 i = ((cc - 1) & ~63u) + lane;
+    if (cc > from && i >= from && i < cc && i < ws.cont_cap) cont[i] = buf;
+    from = cc;
+  };
   if (x < n) {
     u32 m = (u32)min64(x / F.seg, nseg - 1);
     Chain ch;
@@ -549,8 +560,9 @@ __device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ fi
           stopped = true;  // x stays the next candidate
           break;
         }
-        if (cc < ws.cont_cap) cont[cc] = x;  // uniform condition; every lane stores the same value
+        if (lane == (cc & 63u)) buf = x;
         cc++;
+        if ((cc & 63u) == 0) flush();
         x = nx;
         if (x >= n) break;  // reached the end of the stream: conv_chain = nseg
         const u32 m2 = (u32)min64(x / F.seg, nseg - 1);
@@ -564,7 +576,8 @@ __device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ fi
       }
     }
   }
-  if (lane_id() == 0) {
+  flush();
+  if (lane == 0) {
     ws.conv_val[chain] = x;
     ws.conv_chain[chain] = conv_chain;
     ws.conv_idx[chain] = conv_idx;
@@ -655,6 +668,7 @@ __global__ __launch_bounds__(256) void clear_kernel(u32* p, u64 count) {
 
 constexpr u32 kStitchThreads = 1024;  // 16 waves
 constexpr u32 kStitchWaves = kStitchThreads / 64;
+constexpr u32 kStitchLdsRanges = 1024;  // covered ranges the stitch keeps in LDS (more go to global memory only)
 
 // Workgroup-wide exclusive scan of one 64-bit value per thread
 // (kStitchThreads threads): a DPP scan inside each wave, then the wave totals
@@ -683,6 +697,7 @@ __device__ u64 block_exclusive_scan(u64 v, u64* sh, u64& total) {
 __global__ __launch_bounds__(kStitchThreads) void stitch_kernel(const FileDesc* __restrict__ files, ChainWs ws,
                                                                 const u32* __restrict__ multi, u32 nmulti) {
   __shared__ u64 sh[kStitchWaves];
+  __shared__ u32 scov[2 * kStitchLdsRanges];
   __shared__ u32 s_nj, s_nr;
   const u32 t = threadIdx.x;
   const FileDesc& F = files[multi[blockIdx.x]];
@@ -691,48 +706,65 @@ __global__ __launch_bounds__(kStitchThreads) void stitch_kernel(const FileDesc* 
     return;
   }
   const u32 nseg = F.nseg, c0 = F.chain0;
-  u32* jumps = ws.jumps + c0;
+  uint2* jumps = (uint2*)(ws.jumps + 2 * (u64)c0);
   u32* cov = ws.covered + 2 * (u64)c0;
 
-  // 1. boundaries whose continuation skipped at least one whole segment
+  // 1. boundaries whose continuation skipped at least one whole segment,
+  // with the chain each one ends in
   u32 base = 0;
   for (u32 j0 = 0; j0 < nseg; j0 += kStitchThreads) {
     const u32 k = j0 + t;
-    const bool jump = k + 1 < nseg && ws.conv_chain[c0 + k] != k + 1;
+    const u32 nx = k + 1 < nseg ? ws.conv_chain[c0 + k] : 0u;
+    const bool jump = k + 1 < nseg && nx != k + 1;
     u64 tot;
     const u32 pos = (u32)block_exclusive_scan(jump ? 1u : 0u, sh, tot);
-    if (jump) jumps[base + pos] = k;
+    if (jump) jumps[base + pos] = make_uint2(k, nx);
     base += (u32)tot;
   }
   if (t == 0) s_nj = base;
   __syncthreads();
 
-  // 2. walk the jumps in order; a jump from an active chain covers (k, next)
-  if (t == 0) {
+  // 2. walk the jumps in order; a jump from an active chain covers (k, next).
+  // Wave 0 loads 64 jumps at a time and walks them from its lanes, so the
+  // walk waits for memory once per 64 jumps; the ranges also go to LDS while
+  // they fit.
+  if (t < 64) {
+    const u32 nj = s_nj;
     u32 until = 0, nr = 0;
-    for (u32 i = 0; i < s_nj; i++) {
-      const u32 k = jumps[i];
-      if (k < until) continue;  // k itself is covered
-      const u32 nx = ws.conv_chain[c0 + k];
-      cov[2 * nr] = k + 1;
-      cov[2 * nr + 1] = nx;  // covered: k+1 .. nx-1
-      nr++;
-      until = nx;
+    for (u32 i0 = 0; i0 < nj; i0 += 64) {
+      const uint2 jv = i0 + t < nj ? jumps[i0 + t] : make_uint2(0u, 0u);
+      const u32 m = nj - i0 < 64 ? nj - i0 : 64u;
+      for (u32 q = 0; q < m; q++) {
+        const u32 k = readlane(jv.x, q);
+        if (k < until) continue;  // k itself is covered
+        const u32 nx = readlane(jv.y, q);
+        if (t == 0) {
+          cov[2 * nr] = k + 1;
+          cov[2 * nr + 1] = nx;  // covered: k+1 .. nx-1
+          if (nr < kStitchLdsRanges) {
+            scov[2 * nr] = k + 1;
+            scov[2 * nr + 1] = nx;
+          }
+        }
+        nr++;
+        until = nx;
+      }
     }
-    s_nr = nr;
+    if (t == 0) s_nr = nr;
   }
   __syncthreads();
   const u32 nr = s_nr;
+  const bool in_lds = nr <= kStitchLdsRanges;
 
   // 3. active flags; 4. entry index of each active chain
   for (u32 j = t; j < nseg; j += kStitchThreads) {
     u32 lo = 0, hi = nr;  // first range with start > j
     while (lo < hi) {
       u32 mid = (lo + hi) >> 1;
-      if (cov[2 * mid] <= j) lo = mid + 1;
+      if ((in_lds ? scov[2 * mid] : cov[2 * mid]) <= j) lo = mid + 1;
       else hi = mid;
     }
-    const bool covered = lo > 0 && j < cov[2 * (lo - 1) + 1];
+    const bool covered = lo > 0 && j < (in_lds ? scov[2 * (lo - 1) + 1] : cov[2 * (lo - 1) + 1]);
     ws.active[c0 + j] = covered ? 0u : 1u;
     if (j == 0) ws.entry_idx[c0] = 0;
   }

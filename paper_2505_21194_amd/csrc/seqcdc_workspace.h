@@ -22,7 +22,7 @@ struct ChainWs {
   u32* active;         // stitch: chain contributes to the output
   i32* entry_idx;      // stitch: index of the chain's first exact cut (-1 = segment start)
   u64* out_off;        // stitch: output offset of the chain's part
-  u32* jumps;          // stitch scratch: boundaries whose continuation passed a whole segment
+  u32* jumps;          // stitch scratch: (boundary, target chain) pairs of continuations that passed a whole segment
   u32* covered;        // stitch scratch: covered ranges (pairs)
   const u32* stall;    // nonzero: a pass A could not finish (never expected); the results are void
 };
