@@ -725,18 +725,23 @@ __global__ __launch_bounds__(kStitchThreads) void stitch_kernel(const FileDesc* 
   __syncthreads();
 
   // 2. walk the jumps in order; a jump from an active chain covers (k, next).
-  // Wave 0 loads 64 jumps at a time and walks them from its lanes, so the
-  // walk waits for memory once per 64 jumps; the ranges also go to LDS while
-  // they fit.
+  // Wave 0 loads 64 jumps at a time into its lanes and goes from one active
+  // jump straight to the next (the first whose chain is not covered, by
+  // ballot), so the walk waits for memory once per 64 jumps; the ranges also
+  // go to LDS while they fit.
   if (t < 64) {
     const u32 nj = s_nj;
     u32 until = 0, nr = 0;
     for (u32 i0 = 0; i0 < nj; i0 += 64) {
-      const uint2 jv = i0 + t < nj ? jumps[i0 + t] : make_uint2(0u, 0u);
-      const u32 m = nj - i0 < 64 ? nj - i0 : 64u;
-      for (u32 q = 0; q < m; q++) {
+      const bool valid = i0 + t < nj;
+      const uint2 jv = valid ? jumps[i0 + t] : make_uint2(0u, 0u);
+      u64 left = ballot(valid);  // lanes not walked past yet
+      for (;;) {
+        const u64 cand = left & ballot(jv.x >= until);  // k >= until: k itself is not covered
+        if (!cand) break;
+        const u32 q = ctz64(cand);
+        left = q < 63 ? left & (~0ull << (q + 1)) : 0ull;
         const u32 k = readlane(jv.x, q);
-        if (k < until) continue;  // k itself is covered
         const u32 nx = readlane(jv.y, q);
         if (t == 0) {
           cov[2 * nr] = k + 1;
