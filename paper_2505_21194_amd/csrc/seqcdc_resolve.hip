@@ -42,6 +42,18 @@ constexpr u32 kSubBytes = 4096;  // input bytes per sub-window: 64 groups, one p
 constexpr u32 kRing = 8;         // LDS slots per wave: sub-window w lives in slot w % kRing
 
 __device__ __forceinline__ u64 min64(u64 a, u64 b) { return a < b ? a : b; }
+
+// A wave-uniform 32-bit value the optimiser may not look through (an empty
+// asm statement, no instruction): compares built from the 32-bit halves of a
+// 64-bit value stay scalar compares.  The scalar unit has no ordered 64-bit
+// compare, and recombined into one they would run on the vector unit.
+__device__ __forceinline__ u32 opaque_u32(u32 v) {
+  asm("" : "+s"(v));
+  return v;
+}
+
+// a < b for 64-bit positions less than 2^63 apart, on the scalar unit.
+__device__ __forceinline__ bool before(u64 a, u64 b) { return opaque_u32((u32)((a - b) >> 32)) >= 0x80000000u; }
 __device__ __forceinline__ u64 max64(u64 a, u64 b) { return a > b ? a : b; }
 
 // Position of the k-th (1-based) set bit of a wave-uniform word w: lane b
@@ -298,14 +310,17 @@ __device__ void summary_extend(Chain& ch, u32 b) {
 
 // 1 if no block in [b, ceil(L/1024)) holds a run end, 0 if one does, -1 if
 // the answer needs bits that are not marked and cannot be waited for.  Uses
-// and extends the summary knowledge; cheap when it already covers b.
+// and extends the summary knowledge; cheap when it already covers b.  Block
+// indices are compared in 32 bits: sum_to * 1024 >= L exactly when
+// sum_to >= ceil(L / 1024).
 __device__ __forceinline__ int no_end_before(Chain& ch, u32 b, u64 L) {
+  const u32 lb = (u32)((L + 1023) >> 10);
   if (!(ch.sum_from <= b && b <= ch.sum_to)) summary_extend(ch, b);
-  while (!ch.sum_hit && ((u64)ch.sum_to << 10) < L) {
+  while (!ch.sum_hit && ch.sum_to < lb) {
     if (ch.sum_to >= ch.ready_blk && !make_ready(ch, ch.sum_to + 1)) return -1;
     summary_extend(ch, ch.sum_to);
   }
-  return ((u64)ch.sum_to << 10) >= L ? 1 : 0;
+  return ch.sum_to >= lb ? 1 : 0;
 }
 
 // Opposing pairs of the window at positions < pos (0 <= pos <= 4096).
@@ -347,9 +362,13 @@ __device__ __forceinline__ u32 nth_opposing(const Chain& ch, u32 pr, u32 need, u
 // kStop: inside the pipeline kernel, the bits needed are not marked yet and
 // cannot be waited for.
 __device__ u64 next_cut(Chain& ch, u64 c) {
-  if (c >= ch.n) return ch.n;  // callers never ask past the end; keeps every loop progressing
+  // rem = n - c, tested on its 32-bit halves (scalar compares): c >= n makes
+  // it zero or wrap to a huge value (the top bit set, as streams are shorter
+  // than 2^63 bytes)
   const u64 rem = ch.n - c;
-  const u32 lim = rem > ch.max_size ? ch.max_size : (u32)rem;  // Sec. IV limit
+  const u32 rem_hi = opaque_u32((u32)(rem >> 32)), rem_lo = opaque_u32((u32)rem);
+  if (rem_hi >= 0x80000000u || (rem_hi == 0 && rem_lo == 0)) return ch.n;  // callers never ask past the end
+  const u32 lim = (rem_hi != 0 || rem_lo > ch.max_size) ? ch.max_size : rem_lo;  // Sec. IV limit
   u32 s = ch.min_size - ch.sl;                                 // Sec. III-B scan start
   u32 p = s + 1;                                                    // next pair (p-1, p) to examine
   u32 need = ch.trig;                                               // opposing pairs still to the trigger
@@ -441,7 +460,7 @@ __device__ __forceinline__ u64 run_pass_a(const FileDesc* __restrict__ files, co
         const u64 i = ((cnt - 1) & ~63ull) + lane;
         if (i < cnt && i < cap) dst[i] = buf;
       }
-    } while (c < Send);
+    } while (before(c, Send));
   }
   if (lane == 0) {
     if (stalled) pw->resume[kStall] = 1;
@@ -530,6 +549,8 @@ __device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ fi
   };
   if (x < n) {
     u32 m = (u32)min64(x / F.seg, nseg - 1);
+    u64 Sm = (u64)m * F.seg;                          // start of chain m's segment
+    u64 m_end = m + 1 < nseg ? Sm + F.seg : ~0ull;    // start of the next one (none after the last)
     Chain ch;
     chain_init(ch, F, win);
     if (pw) chain_pipe(ch, F, pw, (u32)(((u64)m * F.seg) >> 10));  // reads start past x >= m * seg
@@ -548,7 +569,6 @@ __device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ fi
       stopped = true;
     } else {
       for (;;) {
-        const u64 Sm = (u64)m * F.seg;
         const i32 idx = (x == Sm) ? -1 : cursor_find(lc, x);
         if (x == Sm || idx >= 0) {
           conv_chain = m;
@@ -565,9 +585,10 @@ __device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ fi
         if ((cc & 63u) == 0) flush();
         x = nx;
         if (x >= n) break;  // reached the end of the stream: conv_chain = nseg
-        const u32 m2 = (u32)min64(x / F.seg, nseg - 1);
-        if (m2 != m) {
-          m = m2;
+        if (x >= m_end) {  // x moved into a later segment: min(x / seg, nseg - 1) > m
+          m = (u32)min64(x / F.seg, nseg - 1);
+          Sm = (u64)m * F.seg;
+          m_end = m + 1 < nseg ? Sm + F.seg : ~0ull;
           if (!open(m)) {
             stopped = true;
             break;
