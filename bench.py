@@ -173,9 +173,16 @@ def serving(seq, torch, dev, streams=4, max_batch=64):
     if seq.lib.seqcdc_server_create(ctypes.byref(cfg), ctypes.byref(h)):
         raise RuntimeError(seq.last_error())
 
+    def passes():
+        v = ctypes.c_uint64()
+        if seq.lib.seqcdc_server_stats(h, None, ctypes.byref(v), None, None):
+            raise RuntimeError(seq.last_error())
+        return v.value
+
     def run(rate_gbs):
         """Submit reqs at Poisson arrival times for an offered load (GB/s); None = all at once."""
         tickets = [None] * nreq
+        p0 = passes()
         if rate_gbs:
             mean = total / nreq
             gaps = rng.exponential(mean / (rate_gbs * 1e9), nreq)
@@ -200,7 +207,8 @@ def serving(seq, torch, dev, streams=4, max_batch=64):
         dt = time.perf_counter() - t0
         lat = np.array(lat)
         return {"offered_GBps": round(rate_gbs, 2) if rate_gbs else None, "GBps": round(total / dt / 1e9, 2),
-                "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+                "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "passes": passes() - p0}
 
     try:
         run(None)  # warm-up
