@@ -4,6 +4,7 @@
   modes, 8 / 16 / 32 KiB averages (Table I), with the default plan (the configuration bench.py times).
 * A 256 MiB uniform base plus 9 versions of 200 seeded edits each, chunked in one batch at 4..64 KiB averages:
   every boundary list and the space savings of Eq. 1.
+* 512 MiB uniform in 64 KiB segments: more covered ranges than the stitch keeps in LDS.
 * 4096 files with log-normal sizes (median 256 KiB, sigma 1.5, 4 KiB..64 MiB), each a mixed stream of its own
   seed, at a 16 KiB average: the eager batched call and its prepared hipGraph replay.
 """
@@ -49,6 +50,28 @@ def test_plain_1gib_mixed(env, stream_1g, avg_kib, mode):
     p.mode = mode
     _say("plain 1 GiB mixed, avg", avg_kib, "KiB, mode", mode)
     got = seq.chunk(dev, p).cpu().numpy().astype(np.uint64)
+    want = oracle.chunk(host, **_pd(p))
+    assert got.size == want.size and np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_many_covered_ranges_512mib(env, mode):
+    """512 MiB uniform at an 8 KiB average in the smallest segments (64 KiB): about half the 8192 boundaries
+    jump a whole segment, and the active jumps (covered ranges) outnumber the 1024 the stitch keeps in LDS
+    (about 1900, counted with oracle paths from every segment start), so its walk spans many 64-jump batches
+    and its range search falls back to global memory."""
+    torch, seq = env
+    host = synth.uniform(512 << 20, seed=3)
+    dev = torch.from_numpy(host).cuda()
+    p = seq.seqcdc_params_for_avg(8192)
+    plan = seq.seqcdc_plan_create()
+    try:
+        seq.seqcdc_plan_set_tuning(plan, segment_bytes=64 << 10)
+        seq.seqcdc_plan_set_mode(plan, mode)
+        _say("512 MiB uniform, 64 KiB segments, mode", mode)
+        got = seq.chunk(dev, p, plan=plan).cpu().numpy().astype(np.uint64)
+    finally:
+        seq.seqcdc_plan_destroy(plan)
     want = oracle.chunk(host, **_pd(p))
     assert got.size == want.size and np.array_equal(got, want)
 
