@@ -401,9 +401,9 @@ __device__ u64 next_cut(Chain& ch, u64 c) {
       }
       if (pt < kSubBytes) {  // Sec. III-C: skip SkipSize bytes after the trigger byte
         if (pt >= lw) return c + lim;
-        const u64 s64 = (u64)(w + pt) + 1 + ch.skip;  // relative to c
-        if (s64 >= lim) return c + lim;
-        s = (u32)s64;
+        const u32 rel = w + pt + 1;  // just past the trigger, relative to c: rel <= lim as pt < lw
+        if (ch.skip >= lim - rel) return c + lim;  // the scan would restart at or past the limit
+        s = rel + ch.skip;
         p = s + 1;
         need = ch.trig;
         if (p - w < kSubBytes) continue;  // the scan resumes in this window
@@ -456,7 +456,7 @@ __device__ __forceinline__ u64 run_pass_a(const FileDesc* __restrict__ files, co
       }
       if (lane == (u32)(cnt & 63)) buf = c;
       cnt++;
-      if ((cnt & 63) == 0 || c >= Send) {  // flush the lanes filled since the last flush
+      if ((cnt & 63) == 0 || !before(c, Send)) {  // flush the lanes filled since the last flush
         const u64 i = ((cnt - 1) & ~63ull) + lane;
         if (i < cnt && i < cap) dst[i] = buf;
       }
