@@ -58,6 +58,11 @@ struct Plan {
   HostBuf staging, readback;
   hipEvent_t call_done = nullptr, upload_done = nullptr;
   bool pending = false, upload_pending = false;
+  // the last tables uploaded, and the device buffer (address, capacity) they
+  // went to: a call whose staged tables are the same bytes skips the copy
+  std::vector<char> uploaded;
+  const void* uploaded_dev = nullptr;
+  size_t uploaded_cap = 0;
   hipStream_t last_stream = nullptr;
   u32 last_nchains = 0, last_multi = 0;
   u64 seg_override = 0;

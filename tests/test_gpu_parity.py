@@ -190,6 +190,31 @@ def test_determinism_repeated(env, tiny_plan):
         assert np.array_equal(_gpu_cuts(env, data, P(), plan=tiny_plan), first)
 
 
+def test_one_plan_alternating_layouts_and_rewritten_input(env):
+    """One plan, one input buffer and one output buffer: calls alternate between two layouts (sizes and
+    parameters), and same-layout calls follow a rewrite of the input bytes in place.  A call whose tables
+    equal the last upload skips the copy, so every result is checked against the oracle on its own data."""
+    torch, seq = env
+    plan = seq.seqcdc_plan_create()
+    try:
+        seq.seqcdc_plan_set_tuning(plan, segment_bytes=64 << 10)
+        buf = torch.empty(6 << 20, dtype=torch.uint8, device="cuda")
+        layouts = [(6 << 20, P()), (5 << 20, P(mn=2048, mx=8192, trig=55))]
+        cap = max(seq.seqcdc_max_cuts(n, seq.seqcdc_params(**p)) for n, p in layouts)
+        out = torch.empty(cap, dtype=torch.int64, device="cuda")
+        for step, (li, seed) in enumerate([(0, 1), (0, 2), (1, 3), (0, 4), (1, 5), (1, 6)]):
+            n, params = layouts[li]
+            data = synth.mixed(n, seed=seed)
+            buf[:n].copy_(torch.from_numpy(data).cuda())
+            _say("alternating layouts, step", step, "layout", li, "seed", seed)
+            cnt = seq.seqcdc_chunk(buf.data_ptr(), n, seq.seqcdc_params(**params), out.data_ptr(), cap, plan=plan)
+            got = out[:cnt].cpu().numpy().astype(np.uint64)
+            want = oracle.chunk(data, **params)
+            assert got.size == want.size and np.array_equal(got, want), (step, got.size, want.size)
+    finally:
+        seq.seqcdc_plan_destroy(plan)
+
+
 # ------------------------------------------------------------------ batched path
 @pytest.mark.parametrize("seed", [0, 1])
 def test_batch_matches_oracle(env, seed):
