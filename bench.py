@@ -391,6 +391,25 @@ def main():
     log("mark: %s" % roofline)
 
     extra = {"phases_ms": phases}
+    # context: the same stream as a prepared one-file batch replayed as a hipGraph (one submission, the count
+    # left on the device); `value` stays the plain call, which returns the count to the host
+    gcounts = torch.zeros(1, dtype=torch.int64, device=dev)
+    gb = seq.seqcdc_batch_prepare([(d.data_ptr(), n, 0)], [p], cuts.data_ptr(), [0, cap], gcounts.data_ptr(),
+                                  settings=plan)
+    try:
+        for _ in range(args.warmup):
+            seq.seqcdc_batch_launch(gb, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            seq.seqcdc_batch_launch(gb, stream=stream)
+        torch.cuda.synchronize()
+        gdt = (time.perf_counter() - t0) / args.steps
+    finally:
+        seq.seqcdc_batch_destroy(gb)
+    extra["plain_graph"] = {"ms_per_step": round(gdt * 1e3, 4), "GBps": round(n / gdt / 1e9, 1),
+                            "counts_match": int(gcounts.item()) == count}
+    log("plain as a prepared graph: %s" % extra["plain_graph"])
     if not args.no_batch:
         extra["batched"] = batched(seq, torch, stream, plan, args.steps, args.warmup, dev, not args.no_tune)
         log("batched: %s" % extra["batched"])
