@@ -211,7 +211,8 @@ def serving(seq, torch, dev, streams=4, max_batch=64):
                 "passes": passes() - p0}
 
     try:
-        run(None)  # warm-up
+        for _ in range(3):  # warm-up: the passes' buffers grow to the largest batches they meet
+            run(None)
         sat = run(None)
         peak = sat["GBps"]
         loads = [run(frac * peak) for frac in (0.1, 0.4, 0.8)]
