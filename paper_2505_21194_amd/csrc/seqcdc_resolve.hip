@@ -690,6 +690,7 @@ __global__ __launch_bounds__(256) void clear_kernel(u32* p, u64 count) {
 constexpr u32 kStitchThreads = 1024;  // 16 waves
 constexpr u32 kStitchWaves = kStitchThreads / 64;
 constexpr u32 kStitchLdsRanges = 1024;  // covered ranges the stitch keeps in LDS (more go to global memory only)
+constexpr u32 kStitchLdsJumps = 2048;   // jumps the stitch resolves in LDS in parallel (more: walked in order)
 
 // Workgroup-wide exclusive scan of one 64-bit value per thread
 // (kStitchThreads threads): a DPP scan inside each wave, then the wave totals
@@ -719,6 +720,8 @@ __global__ __launch_bounds__(kStitchThreads) void stitch_kernel(const FileDesc* 
                                                                 const u32* __restrict__ multi, u32 nmulti) {
   __shared__ u64 sh[kStitchWaves];
   __shared__ u32 scov[2 * kStitchLdsRanges];
+  __shared__ u32 sjk[kStitchLdsJumps], sjn[kStitchLdsJumps];  // a jump's boundary and target chain
+  __shared__ u32 snext[kStitchLdsJumps + 1], son[kStitchLdsJumps + 1];
   __shared__ u32 s_nj, s_nr;
   const u32 t = threadIdx.x;
   const FileDesc& F = files[multi[blockIdx.x]];
@@ -739,20 +742,86 @@ __global__ __launch_bounds__(kStitchThreads) void stitch_kernel(const FileDesc* 
     const bool jump = k + 1 < nseg && nx != k + 1;
     u64 tot;
     const u32 pos = (u32)block_exclusive_scan(jump ? 1u : 0u, sh, tot);
-    if (jump) jumps[base + pos] = make_uint2(k, nx);
+    if (jump) {
+      jumps[base + pos] = make_uint2(k, nx);
+      if (base + pos < kStitchLdsJumps) {
+        sjk[base + pos] = k;
+        sjn[base + pos] = nx;
+      }
+    }
     base += (u32)tot;
   }
   if (t == 0) s_nj = base;
   __syncthreads();
 
-  // 2. walk the jumps in order; a jump from an active chain covers (k, next).
-  // Wave 0 loads 64 jumps at a time into its lanes and goes from one active
-  // jump straight to the next (the first whose chain is not covered, by
-  // ballot), so the walk waits for memory once per 64 jumps; the ranges also
-  // go to LDS while they fit.
-  if (t < 64) {
-    const u32 nj = s_nj;
-    u32 until = 0, nr = 0;
+  // 2. the active jumps: a jump from an active chain covers (k, next), and
+  // the first jump is active.  In order, the next active jump after jump i
+  // is the first later one whose boundary its range does not cover, its
+  // successor.  The active jumps are the successors of jump 0, repeatedly.
+  const u32 nj = s_nj;
+  u32 nr = 0;
+  if (nj <= kStitchLdsJumps) {
+    // In LDS, in parallel: each jump's successor by binary search over the
+    // boundaries (increasing), then the jumps reachable from jump 0 by pointer
+    // doubling, then the ranges of the marked jumps in order by a scan.
+    // Index nj stands for "no successor".
+    for (u32 i = t; i < nj; i += kStitchThreads) {
+      const u32 target = sjn[i];
+      u32 lo = i + 1, hi = nj;  // first later jump with boundary >= target
+      while (lo < hi) {
+        const u32 mid = (lo + hi) >> 1;
+        if (sjk[mid] < target) lo = mid + 1;
+        else hi = mid;
+      }
+      snext[i] = lo;
+      son[i] = i == 0 ? 1u : 0u;
+    }
+    if (t == 0) {
+      snext[nj] = nj;
+      son[nj] = 0u;
+    }
+    __syncthreads();
+    // after the round with step 2^r, every jump within 2^(r+1) - 1 successors
+    // of jump 0 is marked (and only such jumps: marks only follow successors)
+    for (u32 step = 1; step < nj; step <<= 1) {
+      u32 nv[kStitchLdsJumps / kStitchThreads];
+#pragma unroll
+      for (u32 q = 0; q < kStitchLdsJumps / kStitchThreads; q++) {
+        const u32 i = t + q * kStitchThreads;
+        nv[q] = i < nj ? snext[i] : nj;
+        if (i < nj && son[i]) son[nv[q]] = 1u;
+      }
+      __syncthreads();
+      u32 n2[kStitchLdsJumps / kStitchThreads];
+#pragma unroll
+      for (u32 q = 0; q < kStitchLdsJumps / kStitchThreads; q++) n2[q] = snext[nv[q]];
+      __syncthreads();
+#pragma unroll
+      for (u32 q = 0; q < kStitchLdsJumps / kStitchThreads; q++) {
+        const u32 i = t + q * kStitchThreads;
+        if (i < nj) snext[i] = n2[q];
+      }
+      __syncthreads();
+    }
+    for (u32 j0 = 0; j0 < nj; j0 += kStitchThreads) {
+      const u32 i = j0 + t;
+      const bool act = i < nj && son[i] != 0u;
+      u64 tot;
+      const u32 pos = nr + (u32)block_exclusive_scan(act ? 1u : 0u, sh, tot);
+      if (act) {
+        cov[2 * pos] = sjk[i] + 1;
+        cov[2 * pos + 1] = sjn[i];  // covered: k+1 .. nx-1
+        if (pos < kStitchLdsRanges) {
+          scov[2 * pos] = sjk[i] + 1;
+          scov[2 * pos + 1] = sjn[i];
+        }
+      }
+      nr += (u32)tot;
+    }
+  } else if (t < 64) {
+    // Too many for LDS: wave 0 walks them in order, 64 at a time from its
+    // lanes, going from one active jump straight to the next by ballot.
+    u32 until = 0, wn = 0;
     for (u32 i0 = 0; i0 < nj; i0 += 64) {
       const bool valid = i0 + t < nj;
       const uint2 jv = valid ? jumps[i0 + t] : make_uint2(0u, 0u);
@@ -765,21 +834,21 @@ __global__ __launch_bounds__(kStitchThreads) void stitch_kernel(const FileDesc* 
         const u32 k = readlane(jv.x, q);
         const u32 nx = readlane(jv.y, q);
         if (t == 0) {
-          cov[2 * nr] = k + 1;
-          cov[2 * nr + 1] = nx;  // covered: k+1 .. nx-1
-          if (nr < kStitchLdsRanges) {
-            scov[2 * nr] = k + 1;
-            scov[2 * nr + 1] = nx;
+          cov[2 * wn] = k + 1;
+          cov[2 * wn + 1] = nx;  // covered: k+1 .. nx-1
+          if (wn < kStitchLdsRanges) {
+            scov[2 * wn] = k + 1;
+            scov[2 * wn + 1] = nx;
           }
         }
-        nr++;
+        wn++;
         until = nx;
       }
     }
-    if (t == 0) s_nr = nr;
+    if (t == 0) s_nr = wn;
   }
   __syncthreads();
-  const u32 nr = s_nr;
+  if (nj > kStitchLdsJumps) nr = s_nr;
   const bool in_lds = nr <= kStitchLdsRanges;
 
   // 3. active flags; 4. entry index of each active chain
