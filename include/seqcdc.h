@@ -93,17 +93,8 @@ int seqcdc_plan_get_tuning(seqcdc_plan* plan, uint64_t n, const seqcdc_params* p
                            uint32_t* mark_span_blocks, uint32_t* waves_per_cu);
 
 /* How a plan runs the resolve stage.  0 (the default): marking, pass A
- * (chains) and pass B (continuations) are separate launches.  1: one
- * persistent pipeline kernel hands out the marking of spans and the chains of
- * every segment from one ordered list, so chains start while later parts of
- * the input are still being marked and each chain continues past its segment
- * as soon as the next chain's cut list exists; every published span costs an
- * L2 write-back on its XCD, which makes this mode slower on MI355X at the
- * sizes measured so far.  2: the mark kernel, then one persistent pipeline
- * kernel of chains only, in which each chain continues past its segment as
- * soon as the next chain's list is published (one release per chain), so a
- * long continuation does not wait for every other chain.  All modes give the
- * same cuts. */
+ * (chains) and pass B (continuations) are separate launches.  All modes give
+ * the same cuts. */
 int seqcdc_plan_set_mode(seqcdc_plan* plan, int mode);
 
 /* Overlapped batches (mode 0 only): the files of a seqcdc_chunk_batch call
@@ -122,29 +113,11 @@ int seqcdc_plan_set_mode(seqcdc_plan* plan, int mode);
  * batches (below) do not overlap. */
 int seqcdc_plan_set_overlap(seqcdc_plan* plan, uint32_t groups);
 
-/* Bound of the waits inside the pipeline modes (1 and 2): a wave waiting for
- * a flag (marked span, published chain list) sleeps briefly up to `rounds`
- * times, then falls back (a continuation is left to the resume kernel; a
- * chain that cannot get its bits stops, and the call reports an error).
- * 0 = default (2^20 rounds, never reached in practice).  Small values force
- * the fallbacks, for testing failure handling. */
-int seqcdc_plan_set_wait_limit(seqcdc_plan* plan, uint32_t rounds);
-
-/* Diagnostics of the plan's last pipeline-mode call (waits for it): out3[0] =
- * continuations the pipeline kernel left to the resume kernel (they reached
- * work not handed out yet), out3[1] = bounded waits that ran out (expected
- * 0), out3[2] = 1 if a chain could not finish (expected 0; the call then
- * reports an error).  All 0 after a phased-mode call. */
-int seqcdc_plan_stats(seqcdc_plan* plan, uint64_t* out3);
-
 /* Per-phase timing of the plan's calls (off by default; on adds HIP events
  * to every call).  seqcdc_plan_phase_ms waits for the plan's last timed call
- * and writes 4 durations in milliseconds.  Mode 0: the mark kernel (events
- * right before and after its launch), pass A (speculative chains),
- * pass B (continuations), stitch + compaction.  Mode 1: the pipeline kernel,
- * 0, the resume kernel (continuations the pipeline left), stitch +
- * compaction.  Mode 2: the mark kernel, the chain pipeline kernel, the resume
- * kernel, stitch + compaction.  Overlapped batches: the marking of
+ * and writes 4 durations in milliseconds: the mark kernel (events right
+ * before and after its launch), pass A (speculative chains), pass B
+ * (continuations), stitch + compaction.  Overlapped batches: the marking of
  * all groups on the caller's stream, then what each later step added after
  * the previous one ended (chains of the last group, the continuations, stitch
  * + compaction).  The values after the first are 0 when no stream had more
@@ -152,8 +125,8 @@ int seqcdc_plan_stats(seqcdc_plan* plan, uint64_t* out3);
 int seqcdc_plan_set_timing(seqcdc_plan* plan, int on);
 int seqcdc_plan_phase_ms(seqcdc_plan* plan, float* ms4);
 
-/* Autotuner: time candidate segment sizes, mark spans, resolve occupancies and
- * the two resolve modes on the given device-resident sample stream, and keep
+/* Autotuner: time candidate segment sizes, mark spans and resolve occupancies
+ * on the given device-resident sample stream, and keep
  * the fastest in a process-wide cache keyed by (arch, CU count, seq_length,
  * average class), which plans consult for settings not set explicitly.
  * Results are exact for every choice; only speed differs.  *best_ms receives

@@ -68,8 +68,6 @@ _SIGS = {
     "seqcdc_plan_set_tuning": ([_p, _u64, _u32, _u32], ctypes.c_int),
     "seqcdc_plan_set_mode": ([_p, ctypes.c_int], ctypes.c_int),
     "seqcdc_plan_set_overlap": ([_p, _u32], ctypes.c_int),
-    "seqcdc_plan_set_wait_limit": ([_p, _u32], ctypes.c_int),
-    "seqcdc_plan_stats": ([_p, ctypes.POINTER(_u64)], ctypes.c_int),
     "seqcdc_plan_set_timing": ([_p, ctypes.c_int], ctypes.c_int),
     "seqcdc_plan_phase_ms": ([_p, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "seqcdc_plan_get_tuning": ([_p, _u64, ctypes.POINTER(seqcdc_params), ctypes.POINTER(_u64),
@@ -169,26 +167,13 @@ def seqcdc_plan_set_tuning(plan, segment_bytes=0, mark_span_blocks=0, waves_per_
 
 
 def seqcdc_plan_set_mode(plan, mode):
-    """0: mark, pass A and pass B as separate launches (default); 1: the fused pipeline kernel; 2: the mark kernel, then
-    a pipeline kernel of chains only."""
+    """Resolve mode: 0 = mark kernel, then pass A, pass B, stitch and compaction as separate launches (default)."""
     _check(lib.seqcdc_plan_set_mode(plan, mode))
 
 
 def seqcdc_plan_set_overlap(plan, groups):
     """Overlapped batches: 0 = default, 1 = off, 2..8 file groups whose marking overlaps earlier groups' chains."""
     _check(lib.seqcdc_plan_set_overlap(plan, groups))
-
-
-def seqcdc_plan_set_wait_limit(plan, rounds):
-    """Bound of the pipeline modes' waits (0 = default); small values force their fallbacks."""
-    _check(lib.seqcdc_plan_set_wait_limit(plan, rounds))
-
-
-def seqcdc_plan_stats(plan):
-    """(continuations resumed, bounded waits that ran out, stall flag) of the plan's last pipeline call."""
-    out = (_u64 * 3)()
-    _check(lib.seqcdc_plan_stats(plan, out))
-    return tuple(out)
 
 
 def seqcdc_plan_set_timing(plan, on=True):

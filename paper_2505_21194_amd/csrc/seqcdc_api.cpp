@@ -21,9 +21,6 @@ namespace seqcdc {
 hipError_t launch_mark(const FileDesc* d_files, const u32* d_hint, u64 span_lo, u64 span_hi, u32 span_blocks,
                        hipStream_t st);
 hipError_t launch_clear(u32* p, u64 count, hipStream_t st);
-hipError_t launch_pipe(const FileDesc* d_files, const u32* d_hint, const ChainWs& ws, const PipeWs& pw, u32 groups,
-                       hipStream_t st);
-hipError_t launch_resume(const FileDesc* d_files, const ChainWs& ws, u32* resume, u32 groups, hipStream_t st);
 hipError_t launch_chains(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32* head,
                          u32 groups, hipStream_t st);
 hipError_t launch_continue(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32* head,
@@ -284,14 +281,9 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   // Overlapped batches take the files largest first and cut them into groups
   // of about equal bytes; everything below (spans, chains) is numbered in
   // that order, so each group owns a contiguous range of spans and chains.
-  // resolve mode: 0 phased launches; 1 one pipeline kernel that marks and
-  // resolves; 2 the mark kernel, then a pipeline kernel of chains only
-  const int rmode = mark_only ? 0 : pl->mode_for(specs[0].p);
-  const bool fused = rmode == 1 || rmode == 2;
-  const bool premarked = rmode == 2;
   u64 total_n = 0;
   for (u32 f = 0; f < nfiles; f++) total_n += specs[f].n;
-  u32 G = (mark_only || fused) ? 1 : pl->groups_for(nfiles, total_n);
+  u32 G = mark_only ? 1 : pl->groups_for(nfiles, total_n);
   std::vector<u32> perm(nfiles);
   for (u32 f = 0; f < nfiles; f++) perm[f] = f;
   if (G > 1) std::stable_sort(perm.begin(), perm.end(), [&](u32 a, u32 b) { return specs[a].n > specs[b].n; });
@@ -391,44 +383,6 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
       (u32)(std::lower_bound(border.begin(), border.end(), chain_at(gfile.size() > 2 ? gfile[1] : nfiles)) -
             border.begin());
 
-  // fused pipeline: one ordered list of mark spans and chains, largest files
-  // first; a chain comes after every span its pass A can read (bytes below its
-  // segment end plus max_size)
-  const u64 sb = (u64)U * kMarkBlock;
-  std::vector<u32> items, span_pos, chain_pos;
-  if (fused) {
-    std::vector<u32> forder(nfiles);
-    for (u32 f = 0; f < nfiles; f++) forder[f] = f;
-    if (nfiles > 1) std::stable_sort(forder.begin(), forder.end(), [&](u32 a, u32 b) { return fd[a].n > fd[b].n; });
-    items.reserve(spans + nchains);
-    span_pos.assign(spans, 0);
-    chain_pos.assign(nchains, 0);
-    for (u32 f : forder) {
-      const FileDesc& d = fd[f];
-      const u64 nsp = (d.n + sb - 1) / sb;
-      u64 next_span = 0;
-      auto emit_spans = [&](u64 end_byte) {
-        if (premarked) return;
-        const u64 upto = (std::min<u64>(end_byte, d.n) + sb - 1) / sb;
-        for (; next_span < upto; next_span++) {
-          span_pos[d.mark_span0 + next_span] = (u32)items.size();
-          items.push_back((u32)(d.mark_span0 + next_span));
-        }
-      };
-      for (u32 k = 0; k < d.nseg; k++) {
-        const u64 S = (u64)k * d.seg;
-        const u64 len = (k + 1 == d.nseg) ? d.n - S : d.seg;
-        emit_spans(S + len + d.max_size);
-        chain_pos[d.chain0 + k] = (u32)items.size();
-        items.push_back(kItemChain | (d.chain0 + k));
-      }
-      emit_spans(d.n);
-      (void)nsp;
-    }
-    if (spans >= kItemChain || nchains >= kItemChain) return fail(SEQCDC_EINVAL, "batch too large");
-  }
-  const u32 nitems = (u32)items.size();
-
   // ---- device workspace
   int rc;
   if ((rc = pl->eo.reserve(mark_only ? 256 : eo_bytes + 256))) return rc;
@@ -442,11 +396,10 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   const u64 nhint = spans / kHintSpans + 2;
   const size_t table_bytes =
       carve_size({nfiles * sizeof(FileDesc), nchains * 4ull, nchains * 8ull, nchains * 8ull, nchains * 4ull,
-                  border.size() * 4 + 4, multi.size() * 4 + 4, compact.size() * 4 + 4, nitems * 4ull + 4,
-                  span_pos.size() * 4 + 4, chain_pos.size() * 4 + 4, nhint * 4ull});
+                  border.size() * 4 + 4, multi.size() * 4 + 4, compact.size() * 4 + 4, nhint * 4ull});
   if ((rc = pl->tables.reserve(table_bytes))) return rc;
-  // work counters (each on its own cache line); fused: done flags and the resume list
-  const u64 nflags = fused ? 64 + spans + (u64)nchains + 64 + kResumeList + nchains : 16ull * (G + 3);
+  // work counters, each on its own cache line
+  const u64 nflags = 16ull * (G + 2);
   if ((rc = pl->flags.reserve(nflags * 4))) return rc;
 
   // assign device pointers
@@ -472,9 +425,6 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   u32* h_border = carve<u32>(cur, border.size() + 1);
   u32* h_multi = carve<u32>(cur, multi.size() + 1);
   u32* h_compact = carve<u32>(cur, compact.size() + 1);
-  u32* h_items = carve<u32>(cur, nitems + 1);
-  u32* h_span_pos = carve<u32>(cur, span_pos.size() + 1);
-  u32* h_chain_pos = carve<u32>(cur, chain_pos.size() + 1);
   u32* h_hint = carve<u32>(cur, nhint);
   const size_t used = cur - h;
   memcpy(h_files, fd.data(), nfiles * sizeof(FileDesc));
@@ -485,9 +435,6 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   if (!border.empty()) memcpy(h_border, border.data(), border.size() * 4);
   if (!multi.empty()) memcpy(h_multi, multi.data(), multi.size() * 4);
   if (!compact.empty()) memcpy(h_compact, compact.data(), compact.size() * 4);
-  if (nitems) memcpy(h_items, items.data(), nitems * 4ull);
-  if (!span_pos.empty()) memcpy(h_span_pos, span_pos.data(), span_pos.size() * 4);
-  if (!chain_pos.empty()) memcpy(h_chain_pos, chain_pos.data(), chain_pos.size() * 4);
   // span hint: entry i = the file holding span 64 i (the last file past the end)
   for (u32 i = 0; i < nhint; i++) h_hint[i] = nfiles - 1;
   for (u32 f = 0; f < nfiles; f++) {
@@ -535,51 +482,12 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   ws.covered = (u32*)carve<u64>(cc, nchains);
 
   // ---- launches
-  u32* heads = (u32*)pl->flags.p;  // [0] pass A head, [16] pass B head, [32] stall flag of the phased path
-  ws.stall = heads + 32;
-  if (!fused) pl->last_resume = nullptr;
+  u32* heads = (u32*)pl->flags.p;  // [0] pass A head, [16] pass B head
   if (mark_only) {
     HIP_TRY(launch_mark(d_files, d_hint, 0, spans, U, st));
-  } else if (fused) {
-    PipeWs pw;
-    pw.items = (const u32*)dev(h_items);
-    pw.nitems = nitems;
-    pw.span_blocks = U;
-    pw.span_pos = (const u32*)dev(h_span_pos);
-    pw.chain_pos = (const u32*)dev(h_chain_pos);
-    pw.head = heads;
-    pw.span_done = heads + 64;
-    pw.chain_done = pw.span_done + spans;
-    pw.resume = pw.chain_done + nchains + 64;
-    pw.premarked = premarked ? 1u : 0u;
-    pw.wait_rounds = pl->wait_rounds ? pl->wait_rounds : kDefaultWaitRounds;
-    ws.stall = pw.resume + kStall;
-    pl->last_resume = pw.resume;
-    const u32 groups = std::max<u32>(1, pl->cus * waves / kWavesPerGroup);  // 4 independent waves each
-    HIP_TRY(launch_clear(heads, nflags, st));
-    HIP_TRY(timing_mark(pl, 0, st));
-    if (premarked) {
-      HIP_TRY(launch_mark(d_files, d_hint, 0, spans, U, st));
-      HIP_TRY(timing_mark(pl, 1, st));
-      HIP_TRY(launch_pipe(d_files, d_hint, ws, pw, std::max<u32>(1, std::min<u32>(groups, (nchains + 3) / 4)), st));
-      HIP_TRY(timing_mark(pl, 2, st));
-    } else {
-      HIP_TRY(launch_pipe(d_files, d_hint, ws, pw, groups, st));
-      HIP_TRY(timing_mark(pl, 1, st));
-      HIP_TRY(timing_mark(pl, 2, st));
-    }
-    if (!multi.empty()) {
-      HIP_TRY(launch_resume(d_files, ws, pw.resume, pl->cus, st));
-      HIP_TRY(timing_mark(pl, 3, st));
-      HIP_TRY(launch_stitch(d_files, ws, (const u32*)dev(h_multi), (u32)multi.size(), st));
-      HIP_TRY(launch_compact(d_files, ws, (const u32*)dev(h_compact), (u32)compact.size(), st));
-    } else {
-      HIP_TRY(timing_mark(pl, 3, st));
-    }
-    HIP_TRY(timing_mark(pl, 4, st));
   } else if (G == 1) {
     const u32 groups = std::max<u32>(1, pl->cus * waves / kWavesPerGroup);  // 4 independent waves each
-    HIP_TRY(launch_clear(heads, 64, st));
+    HIP_TRY(launch_clear(heads, 32, st));
     HIP_TRY(timing_mark(pl, 0, st));  // the mark phase is the mark kernel alone
     HIP_TRY(launch_mark(d_files, d_hint, 0, spans, U, st));
     HIP_TRY(timing_mark(pl, 1, st));
@@ -604,13 +512,12 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
     // tails are the longest) as soon as its chains are done, then those of
     // the other groups, then stitch and compaction; st joins at the end.
     // Counters: pass A of group g at heads[16 g], pass B at heads[16 G] and
-    // heads[16 (G+1)], the stall flag at heads[16 (G+2)].
+    // heads[16 (G+1)].
     if ((rc = ensure_side(pl))) return rc;
     hipStream_t sa = pl->side[0], sb = pl->side[1];
-    ws.stall = heads + 16 * (G + 2);
     const u32 groups = std::max<u32>(1, pl->cus * waves / kWavesPerGroup);
     HIP_TRY(timing_mark(pl, 0, st));
-    HIP_TRY(launch_clear(heads, 16ull * (G + 3), st));
+    HIP_TRY(launch_clear(heads, 16ull * (G + 2), st));
     for (u32 g = 0; g < G; g++) {
       HIP_TRY(launch_mark(d_files, d_hint, span_at(gfile[g]), span_at(gfile[g + 1]), U, st));
       HIP_TRY(hipEventRecord(pl->ev_mark[g], st));
@@ -701,7 +608,6 @@ int chunk_plan(Plan* pl, const void* d_stream, u64 n, const seqcdc_params* p, u6
   pl->pending = false;
   pl->upload_pending = false;
   *h_count = *(u64*)pl->readback.p;
-  if (*h_count == ~0ull) return fail(SEQCDC_EHIP, "internal error: a resolve chain could not finish");
   if (*h_count > cap) return fail(SEQCDC_ECAPACITY, "need %llu cuts, capacity %llu", (unsigned long long)*h_count,
                                   (unsigned long long)cap);
   return SEQCDC_OK;
@@ -804,7 +710,7 @@ int seqcdc_plan_set_tuning(seqcdc_plan* plan, uint64_t segment_bytes, uint32_t m
 
 int seqcdc_plan_set_mode(seqcdc_plan* plan, int mode) {
   if (!plan) return fail(SEQCDC_EINVAL, "plan is NULL");
-  if (mode < 0 || mode > 2) return fail(SEQCDC_EINVAL, "mode must be 0 (phased), 1 (pipeline) or 2 (chain pipeline)");
+  if (mode != 0) return fail(SEQCDC_EINVAL, "mode must be 0 (marked)");
   Plan* pl = (Plan*)plan;
   std::lock_guard<std::mutex> g(pl->mu);
   pl->mode = mode;
@@ -817,29 +723,6 @@ int seqcdc_plan_set_overlap(seqcdc_plan* plan, uint32_t groups) {
   Plan* pl = (Plan*)plan;
   std::lock_guard<std::mutex> g(pl->mu);
   pl->overlap = groups;
-  return SEQCDC_OK;
-}
-
-int seqcdc_plan_set_wait_limit(seqcdc_plan* plan, uint32_t rounds) {
-  if (!plan) return fail(SEQCDC_EINVAL, "plan is NULL");
-  Plan* pl = (Plan*)plan;
-  std::lock_guard<std::mutex> g(pl->mu);
-  pl->wait_rounds = rounds;
-  return SEQCDC_OK;
-}
-
-int seqcdc_plan_stats(seqcdc_plan* plan, uint64_t* out3) {
-  if (!plan || !out3) return fail(SEQCDC_EINVAL, "NULL argument");
-  Plan* pl = (Plan*)plan;
-  std::lock_guard<std::mutex> g(pl->mu);
-  out3[0] = out3[1] = out3[2] = 0;
-  if (!pl->last_resume) return SEQCDC_OK;
-  if (pl->pending) HIP_TRY(hipEventSynchronize(pl->call_done));
-  u32 v[kResumeList];
-  HIP_TRY(hipMemcpy(v, pl->last_resume, sizeof(v), hipMemcpyDeviceToHost));
-  out3[0] = v[kResumeCount];
-  out3[1] = v[kTimeouts];
-  out3[2] = v[kStall];
   return SEQCDC_OK;
 }
 

@@ -1,6 +1,5 @@
 // Autotuner: picks the segment length of speculative resolution, the mark
-// span, the waves per CU of the persistent chain kernels and the resolve mode
-// (phased launches or the fused pipeline) by timing
+// span and the waves per CU of the persistent chain kernels by timing
 // candidates on a device-resident sample.  Every candidate produces the same
 // cuts; only speed differs.  Results go to a process-wide cache keyed by
 // (arch, CU count, SeqLength, average class).
@@ -92,11 +91,6 @@ extern "C" int seqcdc_autotune(seqcdc_plan* plan, const void* d_sample, uint64_t
     const u32 s = best.span_blocks;
     for (u32 w : {8u, 12u, 20u})
       if ((rc = trial(m, s, w))) break;
-  }
-  for (int m : {1, 2}) {  // the pipeline modes at the best shape so far
-    if (rc) break;
-    pl->mode = m;
-    rc = trial(best.seg_mult, best.span_blocks, best.waves_per_cu);
   }
   pl->mode = saved_mode;
   pl->seg_override = saved_seg;

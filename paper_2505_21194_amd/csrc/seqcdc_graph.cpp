@@ -51,12 +51,11 @@ static int prepare(Plan* settings, const seqcdc_file* files, u32 nfiles, const s
     return rc;
   }
   Plan& pl = b->plan;
-  if (settings) {  // the caller's tuning choices; the phased or pipeline mode as that plan would pick it
+  if (settings) {  // the caller's tuning choices and resolve mode as that plan would pick them
     std::lock_guard<std::mutex> g(settings->mu);
     pl.seg_override = settings->seg_override;
     pl.span_override = settings->span_override;
     pl.waves_override = settings->waves_override;
-    pl.wait_rounds = settings->wait_rounds;
     pl.mode = settings->mode_for(params);
   }
   pl.overlap = 1;  // one stream: the graph is a single chain of kernels

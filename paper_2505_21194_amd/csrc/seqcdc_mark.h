@@ -1,5 +1,4 @@
-// SeqCDC mark step on CDNA4 (gfx950): device functions shared by the
-// stand-alone mark kernel and the pipeline kernel.
+// SeqCDC mark step on CDNA4 (gfx950): device functions of the mark kernel.
 //
 // The vector formulation of Sec. III-D, one wave per 1 KiB block: every byte
 // pair becomes one favourable bit F and one opposing bit O; E, the AND of

@@ -1,7 +1,5 @@
-// SeqCDC mark step on CDNA4 (gfx950): the stand-alone mark kernel, which
-// writes the EO16 bitmaps of a stream without resolving cuts.  The chunking
-// entry points mark inside the pipeline kernel instead, with the same device
-// functions.
+// SeqCDC mark step on CDNA4 (gfx950): the mark kernel, which writes the EO16
+// bitmaps and run-end summary of every file of a call.
 
 #include <hip/hip_runtime.h>
 

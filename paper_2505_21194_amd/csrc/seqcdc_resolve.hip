@@ -14,13 +14,10 @@
 // depends only on the cut's position, so once two chains share a cut they
 // agree from then on.  Pass B continues each chain past its segment until one
 // of its cuts belongs to the chain that owns that position; the stitch then
-// keeps the exact pieces and the compaction writes them out.  In the default
-// (phased) mode every dependency between workgroups is a kernel boundary:
-// mark, pass A, pass B, stitch and compaction are separate launches, and the
-// only shared state inside a launch is its atomic work counter.  The pipeline
-// modes hand out marking and chains (mode 1), or chains only (mode 2), from
-// one ordered list inside a persistent kernel, ordered by agent-scope flags
-// with bounded waits; what a wait cannot get is finished by a resume kernel.
+// keeps the exact pieces and the compaction writes them out.  Every
+// dependency between workgroups is a kernel boundary: mark, pass A, pass B,
+// stitch and compaction are separate launches, and the only shared state
+// inside a launch is its atomic work counter.
 //
 // A chain is one wave, and the waves of a workgroup take chains
 // independently.  Its state is wave-uniform (scalar registers); the lanes
@@ -98,14 +95,9 @@ struct Chain {
   // whether sum_to is a block with a run end (or the end) rather than a horizon
   u32 sum_from, sum_to;
   bool sum_hit, hot;
-  // marking progress when the chain runs inside the pipeline kernel
-  const PipeWs* pw;   // null: every bit of the file exists already
-  u32 ready_blk;      // blocks [.., ready_blk) of the file are marked (a span boundary, or nblocks)
-  u32 span0;          // global index of the file's first mark span
 };
 
 constexpr u32 kNone = 0xFFFFFFFFu;
-constexpr u64 kStop = ~0ull;  // next_cut: the bits needed are not marked and cannot be waited for
 
 __device__ __forceinline__ bool skipping(const Chain& ch) { return ch.trig != kNoSkip; }
 
@@ -131,81 +123,6 @@ __device__ __forceinline__ void chain_init(Chain& ch, const FileDesc& F, SEQCDC_
   ch.sum_from = ch.sum_to = 0;
   ch.sum_hit = false;
   ch.hot = false;
-  ch.pw = nullptr;
-  ch.ready_blk = ch.nblocks;
-  ch.span0 = 0;
-}
-
-// ---------------------------------------------------------------------------
-// Flags between waves of the pipeline kernel.  Waves may sit on different
-// XCDs, whose L2 caches are not coherent with each other: flags are atomics
-// at agent scope, and the data they guard is released and acquired with
-// agent-scope fences (L2 write-back / invalidate).  Every wait is bounded; a
-// wait that runs out (never expected) is counted and the waiter falls back.
-// ---------------------------------------------------------------------------
-
-// Every lane's earlier stores become visible to an acquirer of *flag.
-__device__ __forceinline__ void publish(u32* flag) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  if (lane_id() == 0) __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ u32 load_flag(const u32* flag) {
-  return __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ bool is_set(const u32* flag) { return __builtin_amdgcn_readfirstlane(load_flag(flag)) != 0; }
-
-__device__ __forceinline__ void acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
-
-// The item at list position pos has been handed to a (running) wave.
-__device__ __forceinline__ bool handed_out(const PipeWs& pw, u32 pos) {
-  return __builtin_amdgcn_readfirstlane(load_flag(pw.head)) > pos;
-}
-
-__device__ __forceinline__ void count_timeout(const PipeWs& pw) {
-  if (lane_id() == 0) atomicAdd(&pw.resume[kTimeouts], 1u);
-}
-
-// Pipeline fields of a chain whose reads start at block ready_blk (a span
-// boundary at or before the first byte it reads).
-__device__ __forceinline__ void chain_pipe(Chain& ch, const FileDesc& F, const PipeWs* pw, u32 ready_blk) {
-  ch.pw = pw;
-  ch.ready_blk = (pw->premarked || ready_blk >= ch.nblocks) ? ch.nblocks : ready_blk;
-  ch.span0 = (u32)F.mark_span0;
-}
-
-// Makes sure blocks [ready_blk, need_blk) are marked, reading up to 64 span
-// flags at once.  False if a span still to be marked has not been handed out,
-// or a wait ran out.
-__device__ bool make_ready(Chain& ch, u32 need_blk) {
-  if (!ch.pw) return true;
-  const PipeWs& pw = *ch.pw;
-  const u32 sb = pw.span_blocks;
-  const u32 nsp = (ch.nblocks + sb - 1) / sb;
-  if (need_blk > ch.nblocks) need_blk = ch.nblocks;
-  u32 rounds = 0;
-  while (ch.ready_blk < need_blk) {
-    const u32 s = ch.ready_blk / sb;
-    const u32 i = s + lane_id();
-    const bool open = i < nsp && load_flag(&pw.span_done[ch.span0 + (i < nsp ? i : s)]) == 0;
-    const u64 pending = ballot(open);
-    const u32 k = pending ? ctz64(pending) : 64u;
-    if (k > 0) {
-      acquire();
-      const u32 nr = (s + k) * sb;
-      ch.ready_blk = nr < ch.nblocks ? nr : ch.nblocks;
-      rounds = 0;
-    } else {
-      if (!handed_out(pw, pw.span_pos[ch.span0 + s])) return false;
-      if (++rounds > pw.wait_rounds) {
-        count_timeout(pw);
-        return false;
-      }
-      __builtin_amdgcn_s_sleep(2);
-    }
-  }
-  return true;
 }
 
 // Starts the DMA of sub-window `sub` into its LDS slot (sub % kRing): lane l
@@ -225,9 +142,8 @@ __device__ __forceinline__ void dma_window(const Chain& ch, u32 sub) {
 // cut is usually a few hundred bytes away, and the scan after it starts
 // min_size - SeqLength bytes later).  Windows are entered in increasing
 // order, so the slots of the kRing - 1 windows after `sub` never collide.
-__device__ __forceinline__ bool ensure(Chain& ch, u32 sub, u32 hint) {
-  if (ch.cur == sub) return true;
-  if ((sub + 1) * 4 > ch.ready_blk && ch.ready_blk < ch.nblocks && !make_ready(ch, (sub + 1) * 4)) return false;
+__device__ __forceinline__ void ensure(Chain& ch, u32 sub, u32 hint) {
+  if (ch.cur == sub) return;
   const u32 d = sub - ch.pf_base;
   u32 mask = d < kRing ? ch.pf_mask >> d : 0u;
   if (!(mask & 1u)) dma_window(ch, sub);
@@ -236,13 +152,12 @@ __device__ __forceinline__ bool ensure(Chain& ch, u32 sub, u32 hint) {
   const bool inside = sub * 64u + lane_id() < ch.groups;
   const uint4 v = inside ? make_uint4(w.x, w.y, w.z, w.w) : make_uint4(0, 0, 0, 0);
   mask |= 1u;  // sub itself sits in its slot now
-  // windows worth fetching ahead: sub+1, hint and hint+1, inside the stream and already marked
+  // windows worth fetching ahead: sub+1, hint and hint+1, inside the stream
   u32 want = 2u;
   const u32 hi = hint - sub;  // hint >= sub
   if (hi < kRing - 1) want |= 3u << hi;
   const u32 nwin = (ch.groups + 63) >> 6;
-  const u32 top = ch.ready_blk >= ch.nblocks ? nwin : ch.ready_blk >> 2;  // windows [.., top) exist
-  const u32 room = top > sub ? top - sub : 0u;
+  const u32 room = nwin > sub ? nwin - sub : 0u;
   if (room < kRing) want &= (1u << room) - 1u;
   want &= ~mask;
   mask |= want;
@@ -263,19 +178,17 @@ __device__ __forceinline__ bool ensure(Chain& ch, u32 sub, u32 hint) {
     ch.excl = ch.incl - cnt;
     ch.total = readlane(ch.incl, 63);
   }
-  return true;
 }
 
 // Extend the summary knowledge from block b by one load (up to 1024 blocks,
-// 1 MiB of input, never past the marked part): afterwards blocks [b, sum_to)
-// are known to hold no run end.
+// 1 MiB of input): afterwards blocks [b, sum_to) are known to hold no run
+// end.
 __device__ void summary_extend(Chain& ch, u32 b) {
   const u32 lane = lane_id();
   const u32 nb = ch.nblocks;
-  const u32 rb = ch.ready_blk;  // blocks whose summary exists
   u32 to = b;
   bool hit = b >= nb;
-  if (b < rb) {
+  if (b < nb) {
     const u32 a = b & ~15u;
     const u32 idx = a + 16u * lane;
     // branch-free (keeps the chain state wave-uniform): every lane reads a valid
@@ -290,7 +203,7 @@ __device__ void summary_extend(Chain& ch, u32 b) {
     }
     const u32 lo_sh = idx < b ? b - idx : 0u;  // < 16, only in lane 0
     m &= 0xFFFFu << lo_sh;
-    const u32 room = idx < rb ? rb - idx : 0u;
+    const u32 room = idx < nb ? nb - idx : 0u;
     m = room < 16 ? (m & ((1u << room) - 1u)) : m;
     const u64 bal = ballot(m != 0);
     if (bal) {
@@ -298,7 +211,7 @@ __device__ void summary_extend(Chain& ch, u32 b) {
       to = a + 16u * l + (u32)__builtin_ctz(readlane(m, l));
       hit = true;
     } else {
-      to = a + 1024 < rb ? a + 1024 : rb;
+      to = a + 1024 < nb ? a + 1024 : nb;
       hit = to >= nb;
     }
   }
@@ -308,19 +221,14 @@ __device__ void summary_extend(Chain& ch, u32 b) {
   ch.hot = true;
 }
 
-// 1 if no block in [b, ceil(L/1024)) holds a run end, 0 if one does, -1 if
-// the answer needs bits that are not marked and cannot be waited for.  Uses
-// and extends the summary knowledge; cheap when it already covers b.  Block
-// indices are compared in 32 bits: sum_to * 1024 >= L exactly when
-// sum_to >= ceil(L / 1024).
-__device__ __forceinline__ int no_end_before(Chain& ch, u32 b, u64 L) {
+// True if no block in [b, ceil(L/1024)) holds a run end.  Uses and extends
+// the summary knowledge; cheap when it already covers b.  Block indices are
+// compared in 32 bits: sum_to * 1024 >= L exactly when sum_to >= ceil(L / 1024).
+__device__ __forceinline__ bool no_end_before(Chain& ch, u32 b, u64 L) {
   const u32 lb = (u32)((L + 1023) >> 10);
   if (!(ch.sum_from <= b && b <= ch.sum_to)) summary_extend(ch, b);
-  while (!ch.sum_hit && ch.sum_to < lb) {
-    if (ch.sum_to >= ch.ready_blk && !make_ready(ch, ch.sum_to + 1)) return -1;
-    summary_extend(ch, ch.sum_to);
-  }
-  return ch.sum_to >= lb ? 1 : 0;
+  while (!ch.sum_hit && ch.sum_to < lb) summary_extend(ch, ch.sum_to);
+  return ch.sum_to >= lb;
 }
 
 // Opposing pairs of the window at positions < pos (0 <= pos <= 4096).
@@ -359,8 +267,6 @@ __device__ __forceinline__ u32 nth_opposing(const Chain& ch, u32 pr, u32 need, u
 
 // The cut that follows a cut (or a speculative start) at c.  Wave-uniform.
 // Offsets inside the chunk are 32-bit, relative to c (max_size <= 1 GiB).
-// kStop: inside the pipeline kernel, the bits needed are not marked yet and
-// cannot be waited for.
 __device__ u64 next_cut(Chain& ch, u64 c) {
   // rem = n - c, tested on its 32-bit halves (scalar compares): c >= n makes
   // it zero or wrap to a huge value (the top bit set, as streams are shorter
@@ -379,14 +285,13 @@ __device__ u64 next_cut(Chain& ch, u64 c) {
       const u32 e_lo = s + ch.sl - 1;
       const u32 b = (u32)((c + (e_lo > p ? e_lo : p)) >> 10);
       if (ch.sum_from <= b && b <= ch.sum_to) {
-        const int r = no_end_before(ch, b, c + lim);
-        if (r) return r > 0 ? c + lim : kStop;
+        if (no_end_before(ch, b, c + lim)) return c + lim;
       } else {
         ch.hot = false;
       }
     }
     const u32 sub = (u32)((c + p) / kSubBytes);
-    if (!ensure(ch, sub, (u32)((c + p + ch.min_size - ch.sl) / kSubBytes))) return kStop;
+    ensure(ch, sub, (u32)((c + p + ch.min_size - ch.sl) / kSubBytes));
     const u32 w = sub * kSubBytes - c32;  // window start relative to c (mod 2^32)
     const u32 lw = lim - w < kSubBytes ? lim - w : kSubBytes;  // scan limit inside this window
     // events inside this window; a skip that lands in it continues here
@@ -412,8 +317,7 @@ __device__ u64 next_cut(Chain& ch, u64 c) {
       need -= left;  // no event in this window
       p = w + kSubBytes;
       if (p >= lim) return c + lim;
-      const int r = no_end_before(ch, (u32)((c + p) >> 10), c + lim);  // no run end before the limit?
-      if (r) return r > 0 ? c + lim : kStop;
+      if (no_end_before(ch, (u32)((c + p) >> 10), c + lim)) return c + lim;  // no run end before the limit
       break;
     }
   }
@@ -426,34 +330,23 @@ __device__ u64 next_cut(Chain& ch, u64 c) {
 // Pass A of one chain: cuts from its segment start (taken as a cut) until the
 // first cut at or past the segment end.  A single-segment file writes its
 // output directly; otherwise the cuts, exit cut last, go to the chain's list.
-// Inside the pipeline kernel (pw set) the chain waits for the spans it reads,
-// all handed out before it, and publishes its list; if it could not finish
-// (never expected) the stall flag is raised and the output count says so.
-// Returns the exit cut (kStop if none).
-__device__ __forceinline__ u64 run_pass_a(const FileDesc* __restrict__ files, const ChainWs& ws, u32 chain,
-                                          SEQCDC_LOCAL u32x4* win, const PipeWs* pw) {
+__device__ __forceinline__ void run_pass_a(const FileDesc* __restrict__ files, const ChainWs& ws, u32 chain,
+                                           SEQCDC_LOCAL u32x4* win) {
   const u32 lane = lane_id();
   const FileDesc& F = files[ws.chain_file[chain]];
   const u32 k = chain - F.chain0;
   const u64 S = (u64)k * F.seg;
   const u64 Send = (k + 1 == F.nseg) ? F.n : S + F.seg;
   const bool direct = F.nseg == 1;
-  u64 cnt = 0, c = kStop;
-  bool stalled = false;
+  u64 cnt = 0;
   if (F.n) {
     Chain ch;
     chain_init(ch, F, win);
-    if (pw) chain_pipe(ch, F, pw, (u32)(S >> 10));
     SEQCDC_GLOBAL u64* dst = as_global(direct ? F.out : ws.list + ws.list_off[chain]);
     const u64 cap = direct ? F.out_cap : ~0ull;
-    u64 buf = 0;
-    c = S;
+    u64 buf = 0, c = S;
     do {
       c = next_cut(ch, c);
-      if (c == kStop) {
-        stalled = true;
-        break;
-      }
       if (lane == (u32)(cnt & 63)) buf = c;
       cnt++;
       if ((cnt & 63) == 0 || !before(c, Send)) {  // flush the lanes filled since the last flush
@@ -463,31 +356,9 @@ __device__ __forceinline__ u64 run_pass_a(const FileDesc* __restrict__ files, co
     } while (before(c, Send));
   }
   if (lane == 0) {
-    if (stalled) pw->resume[kStall] = 1;
-    if (direct) *F.out_count = stalled ? ~0ull : cnt;
-    else ws.list_cnt[chain] = stalled ? 0u : (u32)cnt;
+    if (direct) *F.out_count = cnt;
+    else ws.list_cnt[chain] = (u32)cnt;
   }
-  if (pw) publish(&pw->chain_done[chain]);
-  return stalled ? kStop : c;
-}
-
-// Pass A of `chain` is published (pw set: false if it has not been handed
-// out yet, or the wait ran out).
-__device__ __forceinline__ bool need_pass_a(const PipeWs* pw, u32 chain) {
-  if (!pw) return true;
-  if (!is_set(&pw->chain_done[chain])) {
-    if (!handed_out(*pw, pw->chain_pos[chain])) return false;
-    u32 rounds = 0;
-    while (!is_set(&pw->chain_done[chain])) {
-      if (++rounds > pw->wait_rounds) {
-        count_timeout(*pw);
-        return false;
-      }
-      __builtin_amdgcn_s_sleep(2);
-    }
-  }
-  acquire();
-  return true;
 }
 
 // Membership of x in the sorted main part (entries [0, cnt)) of a list,
@@ -524,17 +395,14 @@ __device__ __forceinline__ i32 cursor_find(ListCursor& lc, u64 x) {
 // Pass B of `chain` (not the last of its file): its cuts from x on, cc of
 // them already stored, until one is also a cut of the chain that owns that
 // position (or that chain's segment start).  Starts at the exit cut with
-// cc = 0.  Inside the pipeline kernel (pw set) it stops where it would need a
-// list or bits that are not there yet: (x, cc) is saved and the chain joins
-// the resume list.
+// cc = 0.
 __device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ files, const ChainWs& ws, u32 chain,
-                                                 SEQCDC_LOCAL u32x4* win, const PipeWs* pw, u64 x, u32 cc) {
+                                                 SEQCDC_LOCAL u32x4* win, u64 x, u32 cc) {
   const FileDesc& F = files[ws.chain_file[chain]];
   const u64 n = F.n;
   const u32 nseg = F.nseg;
   u32 conv_chain = nseg;
   i32 conv_idx = -1;
-  bool stopped = false;
   SEQCDC_GLOBAL u64* cont = as_global(ws.cont + ws.cont_off[chain]);
   // Entries [from, cc) wait in the lanes (entry i in lane i % 64) and are
   // stored 64 at a time: a store per cut would make every later wait for a
@@ -553,47 +421,34 @@ __device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ fi
     u64 m_end = m + 1 < nseg ? Sm + F.seg : ~0ull;    // start of the next one (none after the last)
     Chain ch;
     chain_init(ch, F, win);
-    if (pw) chain_pipe(ch, F, pw, (u32)(((u64)m * F.seg) >> 10));  // reads start past x >= m * seg
     ListCursor lc;
     auto open = [&](u32 seg) {
       const u32 cm = F.chain0 + seg;
-      if (!need_pass_a(pw, cm)) return false;
       lc.list = ws.list + ws.list_off[cm];
       const u32 have = ws.list_cnt[cm];
       lc.cnt = have ? have - 1 : 0;  // main part: all but the exit cut
       lc.base = 0;
       lc.loaded = false;
-      return true;
     };
-    if (!open(m)) {
-      stopped = true;
-    } else {
-      for (;;) {
-        const i32 idx = (x == Sm) ? -1 : cursor_find(lc, x);
-        if (x == Sm || idx >= 0) {
-          conv_chain = m;
-          conv_idx = idx;
-          break;
-        }
-        const u64 nx = next_cut(ch, x);
-        if (nx == kStop) {
-          stopped = true;  // x stays the next candidate
-          break;
-        }
-        if (lane == (cc & 63u)) buf = x;
-        cc++;
-        if ((cc & 63u) == 0) flush();
-        x = nx;
-        if (x >= n) break;  // reached the end of the stream: conv_chain = nseg
-        if (x >= m_end) {  // x moved into a later segment: min(x / seg, nseg - 1) > m
-          m = (u32)min64(x / F.seg, nseg - 1);
-          Sm = (u64)m * F.seg;
-          m_end = m + 1 < nseg ? Sm + F.seg : ~0ull;
-          if (!open(m)) {
-            stopped = true;
-            break;
-          }
-        }
+    open(m);
+    for (;;) {
+      const i32 idx = (x == Sm) ? -1 : cursor_find(lc, x);
+      if (x == Sm || idx >= 0) {
+        conv_chain = m;
+        conv_idx = idx;
+        break;
+      }
+      const u64 nx = next_cut(ch, x);
+      if (lane == (cc & 63u)) buf = x;
+      cc++;
+      if ((cc & 63u) == 0) flush();
+      x = nx;
+      if (x >= n) break;  // reached the end of the stream: conv_chain = nseg
+      if (x >= m_end) {  // x moved into a later segment: min(x / seg, nseg - 1) > m
+        m = (u32)min64(x / F.seg, nseg - 1);
+        Sm = (u64)m * F.seg;
+        m_end = m + 1 < nseg ? Sm + F.seg : ~0ull;
+        open(m);
       }
     }
   }
@@ -603,7 +458,6 @@ __device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ fi
     ws.conv_chain[chain] = conv_chain;
     ws.conv_idx[chain] = conv_idx;
     ws.cont_cnt[chain] = cc;
-    if (stopped && pw) pw->resume[kResumeList + atomicAdd(&pw->resume[kResumeCount], 1u)] = chain;
   }
 }
 
@@ -623,7 +477,7 @@ __global__ __launch_bounds__(256) void chains_kernel(const FileDesc* __restrict_
   for (;;) {
     const u32 t = wave_pop(head);
     if (t >= nitems) return;
-    run_pass_a(files, ws, order[t], mine, nullptr);
+    run_pass_a(files, ws, order[t], mine);
   }
 }
 
@@ -637,44 +491,7 @@ __global__ __launch_bounds__(256) void continue_kernel(const FileDesc* __restric
     const u32 t = wave_pop(head);
     if (t >= nitems) return;
     const u32 chain = order[t];
-    run_continuation(files, ws, chain, mine, nullptr, exit_cut(ws, chain), 0);
-  }
-}
-
-// The pipeline kernel: every wave takes items in list order until the list
-// is exhausted (marking a span, or a chain's pass A and then its
-// continuation).  Waves of a workgroup are independent (no barriers).
-__global__ __launch_bounds__(256) void pipe_kernel(const FileDesc* __restrict__ files, const u32* __restrict__ hint,
-                                                   ChainWs ws, PipeWs pw) {
-  __shared__ u32x4 win[kWavesPerGroup][kRing * 64];
-  SEQCDC_LOCAL u32x4* mine = (SEQCDC_LOCAL u32x4*)win[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
-  for (;;) {
-    const u32 t = wave_pop(pw.head);
-    if (t >= pw.nitems) return;
-    const u32 code = pw.items[t];
-    if (code & kItemChain) {
-      const u32 chain = code & ~kItemChain;
-      const u64 x = run_pass_a(files, ws, chain, mine, &pw);
-      const FileDesc& F = files[ws.chain_file[chain]];
-      if (chain + 1 < F.chain0 + F.nseg && x != kStop) run_continuation(files, ws, chain, mine, &pw, x, 0);
-    } else {
-      const FileDesc& F = files[file_of_span(files, hint, code)];
-      mark_span(F, code - F.mark_span0, pw.span_blocks);
-      publish(&pw.span_done[code]);
-    }
-  }
-}
-
-// Finishes the continuations the pipeline kernel stopped; everything is
-// marked and published by now.
-__global__ __launch_bounds__(256) void resume_kernel(const FileDesc* __restrict__ files, ChainWs ws, u32* resume) {
-  __shared__ u32x4 win[kWavesPerGroup][kRing * 64];
-  SEQCDC_LOCAL u32x4* mine = (SEQCDC_LOCAL u32x4*)win[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
-  for (;;) {
-    const u32 t = wave_pop(&resume[kResumeHead]);
-    if (t >= resume[kResumeCount]) return;
-    const u32 chain = __builtin_amdgcn_readfirstlane(resume[kResumeList + t]);
-    run_continuation(files, ws, chain, mine, nullptr, ws.conv_val[chain], ws.cont_cnt[chain]);
+    run_continuation(files, ws, chain, mine, exit_cut(ws, chain), 0);
   }
 }
 
@@ -725,10 +542,6 @@ __global__ __launch_bounds__(kStitchThreads) void stitch_kernel(const FileDesc* 
   __shared__ u32 s_nj, s_nr;
   const u32 t = threadIdx.x;
   const FileDesc& F = files[multi[blockIdx.x]];
-  if (*ws.stall) {  // a pass A could not finish (never expected): report the failure in the count
-    if (t == 0) *F.out_count = ~0ull;
-    return;
-  }
   const u32 nseg = F.nseg, c0 = F.chain0;
   uint2* jumps = (uint2*)(ws.jumps + 2 * (u64)c0);
   u32* cov = ws.covered + 2 * (u64)c0;
@@ -901,7 +714,7 @@ __global__ __launch_bounds__(256) void compact_kernel(const FileDesc* __restrict
   const u32 w = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6));  // wave-uniform
   if (w >= nchains) return;
   const u32 chain = chains[w];
-  if (*ws.stall || !ws.active[chain]) return;
+  if (!ws.active[chain]) return;
   const FileDesc& F = files[ws.chain_file[chain]];
   const u32 j = chain - F.chain0;
   const bool last = j + 1 == F.nseg;
@@ -967,18 +780,6 @@ hipError_t launch_continue(const FileDesc* d_files, const ChainWs& ws, const u32
                            u32 groups, hipStream_t st) {
   if (!nitems) return hipSuccess;
   hipLaunchKernelGGL(continue_kernel, dim3(groups), dim3(256), 0, st, d_files, ws, d_order, nitems, head);
-  return hipGetLastError();
-}
-
-hipError_t launch_pipe(const FileDesc* d_files, const u32* d_hint, const ChainWs& ws, const PipeWs& pw, u32 groups,
-                       hipStream_t st) {
-  if (!pw.nitems) return hipSuccess;
-  hipLaunchKernelGGL(pipe_kernel, dim3(groups), dim3(256), 0, st, d_files, d_hint, ws, pw);
-  return hipGetLastError();
-}
-
-hipError_t launch_resume(const FileDesc* d_files, const ChainWs& ws, u32* resume, u32 groups, hipStream_t st) {
-  hipLaunchKernelGGL(resume_kernel, dim3(groups), dim3(256), 0, st, d_files, ws, resume);
   return hipGetLastError();
 }
 

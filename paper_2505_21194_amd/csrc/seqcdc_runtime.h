@@ -14,7 +14,6 @@ namespace seqcdc {
 
 constexpr u64 kMaxSegments = 65536;  // per stream
 constexpr u32 kMaxGroups = 8;        // file groups of an overlapped batch
-constexpr u32 kDefaultWaitRounds = 1u << 20;  // pipeline waits: rounds of a short sleep before falling back
 constexpr u64 kMaxStream = 1ull << 38;  // 256 GiB: group and sub-window indices stay 32-bit
 
 struct DevBuf {
@@ -67,8 +66,7 @@ struct Plan {
   u32 last_nchains = 0, last_multi = 0;
   u64 seg_override = 0;
   u32 span_override = 0, waves_override = 0;
-  int mode = -1;  // 0: mark, pass A, pass B as separate launches; 1: fused pipeline kernel; -1: tuned (else 0)
-  u32* last_resume = nullptr;  // device resume counters of the last pipeline call
+  int mode = -1;  // resolve mode (0: marked); -1: tuned (else 0)
   // optional per-phase timing of the last call: events before the mark
   // kernel and after the mark, pass A, pass B and stitch + compaction
   bool timing = false, timed = false;
@@ -77,7 +75,6 @@ struct Plan {
   // later groups run on the caller's stream while side[0] runs the chains of
   // earlier ones and side[1] their continuations
   u32 overlap = 0;  // groups (0: default, 1: off)
-  u32 wait_rounds = 0;  // bound of the pipeline modes' waits (0: kDefaultWaitRounds)
   hipStream_t side[2] = {nullptr, nullptr};
   hipEvent_t ev_mark[kMaxGroups] = {};
   hipEvent_t ev_chain_first = nullptr, ev_chain_last = nullptr, ev_join = nullptr;

@@ -221,10 +221,9 @@ int seqcdc_server_create(const seqcdc_server_config* cfg, seqcdc_server** out) {
     Pass* ps = new Pass();
     int rc = plan_init(&ps->plan, dev);
     // Passes are batches of many requests, mostly small, several in flight:
-    // always the phased launches (a pipeline mode tuned on one long stream
-    // would serialise them), no overlapped groups, and a fixed chain
-    // occupancy, so that one pass's persistent chain kernels leave room (LDS,
-    // wave slots) for the others'.
+    // the marked resolve, no overlapped groups, and a fixed chain occupancy,
+    // so that one pass's persistent chain kernels leave room (LDS, wave
+    // slots) for the others'.
     ps->plan.mode = 0;
     ps->plan.overlap = 1;
     ps->plan.waves_override = kServerWaves;

@@ -91,10 +91,8 @@ def test_new_entry_points_reject_bad_arguments_without_gpu_work(seq):
     """Plan knobs, prepared batches and diagnostics check their arguments before touching a device."""
     E = seq.SEQCDC_EINVAL
     assert seq.lib.seqcdc_plan_set_overlap(None, 2) == E
-    assert seq.lib.seqcdc_plan_set_wait_limit(None, 1) == E
     assert seq.lib.seqcdc_plan_set_mode(None, 0) == E
     assert seq.lib.seqcdc_plan_set_timing(None, 1) == E
-    assert seq.lib.seqcdc_plan_stats(None, None) == E
     assert seq.lib.seqcdc_plan_phase_ms(None, None) == E
     assert seq.lib.seqcdc_batch_launch(None, None) == E
     assert seq.lib.seqcdc_batch_destroy(None) == E

@@ -1,7 +1,6 @@
 """Resolve modes, the autotuner and the dedup ratio of a backup-snapshot series.
 
-* The fused pipeline mode (marking and chains in one persistent kernel) gives the same cuts as the oracle
-  and as the phased mode, on the plain and batched paths, and reports no stalled chain or timed-out wait.
+* Every resolve mode gives the oracle's cuts on many small files and on prepared (graph-replayed) batches.
 * Whatever the autotuner picks, the cuts do not change.
 * Config 3 at reduced size: a uniform base plus versions made by seeded edits, chunked on the GPU at
   4/8/16/32/64 KiB averages; the cut lists equal the oracle's and the space savings of Eq. 1 computed by
@@ -14,6 +13,8 @@ import oracle
 import synth
 
 pytestmark = pytest.mark.gpu
+
+MODES = [0]  # resolve modes of seqcdc_plan_set_mode
 
 
 @pytest.fixture(scope="module")
@@ -30,53 +31,6 @@ def _say(*a):
 
 def P(mode=0, sl=5, mn=4096, mx=16384, trig=50, skip=256):
     return dict(mode=mode, seq_length=sl, min_size=mn, max_size=mx, skip_trigger=trig, skip_size=skip)
-
-
-@pytest.mark.parametrize("seg_kib", [64, 1024])
-@pytest.mark.parametrize("gen", ["uniform", "mixed"])
-@pytest.mark.parametrize("pmode", [1, 2])
-def test_fused_mode_plain(env, seg_kib, gen, pmode):
-    torch, seq = env
-    data = (synth.uniform if gen == "uniform" else synth.mixed)(24 << 20, seed=seg_kib)
-    want = oracle.chunk(data, **P())
-    d = torch.from_numpy(data).cuda()
-    outs = {}
-    for mode in (pmode, 0):
-        plan = seq.seqcdc_plan_create()
-        try:
-            seq.seqcdc_plan_set_tuning(plan, segment_bytes=seg_kib << 10)
-            seq.seqcdc_plan_set_mode(plan, mode)
-            _say("plain", gen, "seg", seg_kib, "KiB mode", mode)
-            outs[mode] = seq.chunk(d, P(), plan=plan).cpu().numpy().astype(np.uint64)
-            if mode != 0:
-                resumed, timeouts, stall = seq.seqcdc_plan_stats(plan)
-                assert timeouts == 0 and stall == 0
-        finally:
-            seq.seqcdc_plan_destroy(plan)
-    assert np.array_equal(outs[pmode], want)
-    assert np.array_equal(outs[0], want)
-
-
-@pytest.mark.parametrize("pmode", [1, 2])
-def test_fused_mode_batch(env, pmode):
-    torch, seq = env
-    rng = np.random.default_rng(9)
-    sizes = [int(x) for x in rng.integers(0, 2 << 20, 60)] + [0, 1, 4097, 6 << 20]
-    params = [P(), P(mode=1, sl=6, mn=8192, mx=32768, skip=512)]
-    datas = [synth.mixed(s, seed=500 + i) for i, s in enumerate(sizes)]
-    pidx = [i % 2 for i in range(len(sizes))]
-    tens = [torch.from_numpy(x).cuda() if x.size else torch.zeros(0, dtype=torch.uint8, device="cuda") for x in datas]
-    plan = seq.seqcdc_plan_create()
-    try:
-        seq.seqcdc_plan_set_tuning(plan, segment_bytes=128 << 10)
-        seq.seqcdc_plan_set_mode(plan, pmode)
-        _say("pipeline mode", pmode, "batch", len(sizes), "files")
-        outs = seq.chunk_batch(tens, params, params_index=pidx, plan=plan)
-        assert seq.seqcdc_plan_stats(plan)[1:] == (0, 0)
-    finally:
-        seq.seqcdc_plan_destroy(plan)
-    for i, (x, o) in enumerate(zip(datas, outs)):
-        assert np.array_equal(o.cpu().numpy().astype(np.uint64), oracle.chunk(x, **params[pidx[i]])), i
 
 
 def test_autotune_keeps_results(env):
@@ -147,7 +101,7 @@ def test_overlapped_batch(env, groups):
         seq.seqcdc_plan_destroy(plan)
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", MODES)
 def test_many_small_files(env, mode):
     """Thousands of tiny files, many per 64 mark spans (the span -> file lookup), plus a few large ones."""
     torch, seq = env
@@ -171,7 +125,7 @@ def test_many_small_files(env, mode):
         assert np.array_equal(o.cpu().numpy().astype(np.uint64), oracle.chunk(x, **p)), i
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", MODES)
 def test_prepared_batch_graph_replays(env, mode):
     """A prepared (hipGraph-captured) batch: each replay, with new input contents and eager work in between,
     equals the oracle."""
@@ -218,53 +172,3 @@ def test_prepared_batch_graph_replays(env, mode):
         seq.seqcdc_batch_destroy(batch)
         seq.seqcdc_plan_destroy(settings)
         seq.seqcdc_plan_destroy(other)
-
-
-@pytest.mark.parametrize("pmode", [1, 2])
-def test_pipeline_wait_limit_fallbacks(env, pmode):
-    """Failure handling forced from the host: with the pipeline modes' bounded waits cut to one round, waits run
-    out.  Mode 2 leaves such continuations to the resume kernel and must still give exact cuts; mode 1 may also
-    stop a chain that cannot get its bits, and must then report it (count ~0, stall flag), never wrong cuts.
-    Every kernel exits normally either way."""
-    torch, seq = env
-    rng = np.random.default_rng(300 + pmode)
-    sizes = [int(x) for x in rng.integers(0, 3 << 20, 30)] + [6 << 20, 0, 1]
-    p = P()
-    datas = [synth.mixed(s, seed=7000 + i) for i, s in enumerate(sizes)]
-    tens = [torch.from_numpy(x).cuda() if x.size else torch.zeros(0, dtype=torch.uint8, device="cuda") for x in datas]
-    ps = seq.make_params(**p)
-    offs = [0]
-    for s in sizes:
-        offs.append(offs[-1] + max(seq.seqcdc_max_cuts(s, ps), 1))
-    cuts = torch.zeros(offs[-1], dtype=torch.int64, device="cuda")
-    counts = torch.zeros(len(sizes), dtype=torch.int64, device="cuda")
-    plan = seq.seqcdc_plan_create()
-    try:
-        seq.seqcdc_plan_set_tuning(plan, segment_bytes=128 << 10)
-        seq.seqcdc_plan_set_mode(plan, pmode)
-        seq.seqcdc_plan_set_wait_limit(plan, 1)
-        _say("pipeline mode", pmode, "with one-round waits")
-        seq.seqcdc_chunk_batch([(t.data_ptr(), t.numel(), 0) for t in tens], [ps], cuts.data_ptr(), offs,
-                               counts.data_ptr(), plan=plan)
-        torch.cuda.synchronize()
-        resumed, timeouts, stall = seq.seqcdc_plan_stats(plan)
-        cnt = counts.cpu().numpy().astype(np.uint64)
-        allc = cuts.cpu().numpy().astype(np.uint64)
-        stopped = 0
-        for i, x in enumerate(datas):
-            if cnt[i] == np.uint64(0xFFFFFFFFFFFFFFFF):
-                stopped += 1
-                continue
-            assert np.array_equal(allc[offs[i]:offs[i] + int(cnt[i])], oracle.chunk(x, **p)), i
-        if pmode == 2:
-            assert stopped == 0 and stall == 0
-        else:
-            assert (stopped > 0) == (stall == 1)
-        # the same plan with the default bound again: everything exact
-        seq.seqcdc_plan_set_wait_limit(plan, 0)
-        outs = seq.chunk_batch(tens, [p], plan=plan)
-        for i, (x, o) in enumerate(zip(datas, outs)):
-            assert np.array_equal(o.cpu().numpy().astype(np.uint64), oracle.chunk(x, **p)), i
-        assert seq.seqcdc_plan_stats(plan)[1:] == (0, 0)
-    finally:
-        seq.seqcdc_plan_destroy(plan)
