@@ -57,6 +57,9 @@ class SeqCDCError(RuntimeError):
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libseqcdc.so is not built (run __graft_entry__.build() or paper_2505_21194_amd/build.py)")
+# PyTorch ships its own HIP runtime (same soname as the system one).  Loading torch first makes the library bind to
+# that copy: loaded the other way round, the process would hold two HIP runtimes, and the second sees no device.
+import torch  # noqa: E402,F401
 lib = ctypes.CDLL(LIB_PATH)
 
 _SIGS = {

@@ -14,21 +14,10 @@
 
 #include "../../include/seqcdc.h"
 #include "seqcdc_internal.h"
+#include "seqcdc_launch.h"
 #include "seqcdc_runtime.h"
 
 namespace seqcdc {
-
-hipError_t launch_mark(const FileDesc* d_files, const u32* d_hint, u64 span_lo, u64 span_hi, u32 span_blocks,
-                       hipStream_t st);
-hipError_t launch_clear(u32* p, u64 count, hipStream_t st);
-hipError_t launch_chains(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32* head,
-                         u32 groups, hipStream_t st);
-hipError_t launch_continue(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32* head,
-                           u32 groups, hipStream_t st);
-hipError_t launch_stitch(const FileDesc* d_files, const ChainWs& ws, const u32* d_multi, u32 nmulti,
-                         hipStream_t st);
-hipError_t launch_compact(const FileDesc* d_files, const ChainWs& ws, const u32* d_chains, u32 nchains,
-                          hipStream_t st);
 
 // ---------------------------------------------------------------- errors
 static thread_local std::string g_err;

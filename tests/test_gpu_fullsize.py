@@ -1,7 +1,8 @@
 """Parity at the full sizes of the benchmark workloads, whole outputs against the oracle.
 
 * One 1 GiB mixed backup-like stream (1 MiB blocks: uniform, Zipf text, zero / repeated-pattern runs), both
-  modes, 8 / 16 / 32 KiB averages (Table I), with the default plan (the configuration bench.py times).
+  modes, 8 / 16 / 32 KiB averages (Table I), with the default plan (the configuration bench.py times), and the
+  8 KiB parameters at SeqLength 6 in both modes.
 * A 256 MiB uniform base plus 9 versions of 200 seeded edits each, chunked in one batch at 4..64 KiB averages:
   every boundary list and the space savings of Eq. 1.
 * 512 MiB uniform in 64 KiB segments: more covered ranges than the stitch keeps in LDS.
@@ -49,6 +50,21 @@ def test_plain_1gib_mixed(env, stream_1g, avg_kib, mode):
     p = seq.seqcdc_params_for_avg(avg_kib << 10)
     p.mode = mode
     _say("plain 1 GiB mixed, avg", avg_kib, "KiB, mode", mode)
+    got = seq.chunk(dev, p).cpu().numpy().astype(np.uint64)
+    want = oracle.chunk(host, **_pd(p))
+    assert got.size == want.size and np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_plain_1gib_mixed_seqlength6(env, stream_1g, mode):
+    """SeqLength counted as bytes with 6 in place of Table I's 5 (the reading under which Table I's averages hold
+    on random data), 8 KiB parameters otherwise: many more skips per chunk and max-size cuts."""
+    torch, seq = env
+    host, dev = stream_1g
+    p = seq.seqcdc_params_for_avg(8192)
+    p.seq_length = 6
+    p.mode = mode
+    _say("plain 1 GiB mixed, SeqLength 6, mode", mode)
     got = seq.chunk(dev, p).cpu().numpy().astype(np.uint64)
     want = oracle.chunk(host, **_pd(p))
     assert got.size == want.size and np.array_equal(got, want)

@@ -4,6 +4,8 @@ Covers the mark bitmaps (Sec. III-D masks), the plain chunking path with specula
 stitching and compaction, forced tiny segments and non-converging (periodic / zero-run) data,
 ragged and tiny lengths, misaligned inputs, capacity errors and the batched path.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -181,6 +183,29 @@ def test_capacity_error(env):
         seq.seqcdc_chunk(t.data_ptr(), t.numel(), P(), out.data_ptr(), 10)
     assert ei.value.code == seq.SEQCDC_ECAPACITY and ei.value.count == want.size
     assert np.array_equal(out.cpu().numpy().astype(np.uint64), want[:10])
+
+
+@pytest.mark.parametrize("n", [0, 1, 5000, 3 << 20])
+def test_chunk_host_convenience(env, n):
+    """seqcdc_chunk_host: host bytes in, host cuts out (copies over PCIe around the device path)."""
+    torch, seq = env
+    data = synth.mixed(n, seed=31 + n)
+    p = seq.make_params(**P())
+    cap = max(seq.seqcdc_max_cuts(n, p), 1)
+    out = np.zeros(cap, dtype=np.uint64)
+    cnt = ctypes.c_uint64(99)
+    src = data if data.size else np.zeros(1, np.uint8)
+    rc = seq.lib.seqcdc_chunk_host(ctypes.c_void_p(src.ctypes.data), n, ctypes.byref(p),
+                                   ctypes.c_void_p(out.ctypes.data), cap, ctypes.byref(cnt))
+    assert rc == 0, seq.last_error()
+    want = oracle.chunk(data, **P())
+    assert cnt.value == want.size and np.array_equal(out[:cnt.value], want)
+    if want.size > 2:  # too small an output: the required count, the first cap cuts
+        short = np.zeros(2, dtype=np.uint64)
+        rc = seq.lib.seqcdc_chunk_host(ctypes.c_void_p(src.ctypes.data), n, ctypes.byref(p),
+                                       ctypes.c_void_p(short.ctypes.data), 2, ctypes.byref(cnt))
+        assert rc == seq.SEQCDC_ECAPACITY and cnt.value == want.size
+        assert np.array_equal(short, want[:2])
 
 
 def test_determinism_repeated(env, tiny_plan):

@@ -1,7 +1,8 @@
 """Serving loop: continuous batching over a device-resident request stream.
 
 Each request's cuts must equal the oracle's and the plain per-request path's, whatever else is in flight and in
-whatever order requests arrive; admission never exceeds the memory budget.
+whatever order requests arrive; admission never exceeds the memory budget.  One test runs the serving workload at
+its full sizes: 256 MiB snapshot versions, log-normal request sizes up to 256 MiB, 8 and 32 KiB averages mixed.
 """
 import ctypes
 import random
@@ -146,3 +147,72 @@ def test_serving_errors(env):
         assert res.count == 3 << 20 >> 14  # all-zero bytes: every chunk is cut at the 16 KiB maximum
     finally:
         seq.lib.seqcdc_server_destroy(h)
+
+
+def test_serving_poll_until_done(env):
+    """The non-blocking poll: pending (SEQCDC_EAGAIN) until the pass completes, then the result, then unknown after
+    release."""
+    torch, seq = env
+    params = [seq.seqcdc_params_for_avg(8192)]
+    pd = dict(mode=0, seq_length=5, min_size=4096, max_size=16384, skip_trigger=50, skip_size=256)
+    host = synth.mixed(40 << 20, seed=81)
+    dev = torch.from_numpy(host).cuda()
+    h, keep = _server(seq, params, 512 << 20)
+    try:
+        t = ctypes.c_uint64()
+        assert seq.lib.seqcdc_server_submit(h, ctypes.c_void_p(dev.data_ptr()), host.size, 0, ctypes.byref(t)) == 0
+        res = seq.seqcdc_result()
+        seen_pending = 0
+        t0 = time.perf_counter()
+        while True:
+            rc = seq.lib.seqcdc_server_poll(h, t.value, ctypes.byref(res))
+            if rc == 0:
+                break
+            assert rc == seq.SEQCDC_EAGAIN and res.status == seq.SEQCDC_EAGAIN
+            seen_pending += 1
+            assert time.perf_counter() - t0 < 60.0
+            time.sleep(0.0002)
+        assert res.status == 0 and res.latency_ms >= res.queue_ms >= 0
+        got = np.ctypeslib.as_array(res.cuts, shape=(res.count,)).copy()
+        assert np.array_equal(got, oracle.chunk(host, **pd))
+        assert seq.lib.seqcdc_server_release(h, t.value) == 0
+        assert seq.lib.seqcdc_server_poll(h, t.value, ctypes.byref(res)) == seq.SEQCDC_ENOENT
+    finally:
+        seq.lib.seqcdc_server_destroy(h)
+
+
+def test_serving_full_size_requests(env):
+    """The serving workload at its full sizes: slices of 256 MiB snapshot versions with log-normal sizes (median
+    1 MiB, sigma 1.5, clamped to 1 KiB..256 MiB, several whole-version requests among them), half at the 8 KiB and
+    half at the 32 KiB parameters, all in flight together under a 4 GiB budget; every result equals the oracle's."""
+    torch, seq = env
+    params = [seq.seqcdc_params_for_avg(8192), seq.seqcdc_params_for_avg(32768)]
+    pd = [dict(mode=p.mode, seq_length=p.seq_length, min_size=p.min_size, max_size=p.max_size,
+               skip_trigger=p.skip_trigger, skip_size=p.skip_size) for p in params]
+    vers = synth.snapshot_series(256 << 20, 3, seed=11, nedits=200, maxlen=4096)
+    sizes = synth.lognormal_sizes(240, 1 << 20, 1.5, 1024, 256 << 20, seed=12)
+    picks = synth.uniform_ints(240, len(vers), seed=12, tag=1)
+    reqs = []
+    for i in range(240):
+        v = vers[int(picks[i])]
+        n = int(min(sizes[i], v.size))
+        off = int(synth.uniform_ints(1, v.size - n + 1, seed=1200 + i, tag=2)[0])
+        reqs.append((int(picks[i]), off, n, i % 2))
+    for j, vi in enumerate((0, 2)):  # whole versions (the 256 MiB clamp), one at each average
+        reqs.append((vi, 0, int(vers[vi].size), j))
+    dev_vers = [torch.from_numpy(v).cuda() for v in vers]
+    budget = 4 << 30
+    h, keep = _server(seq, params, budget, slots=256, streams=4, max_batch=64)
+    try:
+        print("[case] serving full size:", len(reqs), "requests,", sum(r[2] for r in reqs) >> 20, "MiB", flush=True)
+        out = _run(seq, h, dev_vers, reqs, list(range(len(reqs))))
+        adm, passes, peak, peak_n = (ctypes.c_uint64() for _ in range(4))
+        seq.lib.seqcdc_server_stats(h, ctypes.byref(adm), ctypes.byref(passes), ctypes.byref(peak),
+                                    ctypes.byref(peak_n))
+        assert adm.value == len(reqs) and peak.value <= budget
+    finally:
+        seq.lib.seqcdc_server_destroy(h)
+    assert max(r[2] for r in reqs) >= 256 << 20
+    for i, (vi, off, n, pi) in enumerate(reqs):
+        want = oracle.chunk(vers[vi][off:off + n], **pd[pi])
+        assert out[i].size == want.size and np.array_equal(out[i], want), i
