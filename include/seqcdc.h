@@ -199,6 +199,29 @@ int seqcdc_batch_destroy(seqcdc_batch* batch);
  * predecessor.  Asynchronous. */
 int seqcdc_mark(const void* d_stream, uint64_t n, const seqcdc_params* p, uint32_t* d_eo, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the plain
+ * path of seqcdc_chunk with every workspace (mark bitmaps, per-segment cut
+ * lists, continuation buffers, chain state, tables, work counters) carved from
+ * one fixed device array of SEQCDC_NOALLOC_SCRATCH_BYTES that the library
+ * holds on each GPU it runs on until the process ends.  The call allocates
+ * nothing (no hipMalloc, hipHostMalloc or frees), copies nothing from the
+ * host and does not wait: it only enqueues kernels on `stream`, the first of
+ * which writes this call's tables and clears its counters.  Results are those
+ * of seqcdc_chunk (same segment length rule, 128 x min_size, at least
+ * 64 KiB; the autotuner's choices are not consulted).
+ * d_count: device pointer receiving the number of cuts; if it exceeds cap,
+ *   only the first cap cuts were written to d_cuts.
+ * Errors: SEQCDC_EINVAL for bad arguments and for streams whose workspace
+ *   (about n/4 + n/64 bytes at the Table I parameters, so up to about 230 MiB
+ *   of input) does not fit the scratch array; the message gives both sizes.
+ * Every call on one GPU uses the same array: calls that overlap on one GPU
+ * (on different streams, or from several threads, without ordering between
+ * them) race and give wrong results. */
+#define SEQCDC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int seqcdc_chunk_noalloc(const void* d_stream, uint64_t n, const seqcdc_params* p, uint64_t* d_cuts, uint64_t cap,
+                         uint64_t* d_count, void* stream);
+
 /* Host convenience: copy h_stream to the device, chunk it, copy the cuts back. */
 int seqcdc_chunk_host(const uint8_t* h_stream, uint64_t n, const seqcdc_params* p, uint64_t* h_cuts, uint64_t cap,
                       uint64_t* h_count);

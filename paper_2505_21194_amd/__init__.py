@@ -22,6 +22,7 @@ SEQCDC_ENOENT = -7
 SEQCDC_INCREASING = 0
 SEQCDC_DECREASING = 1
 SEQCDC_NO_SKIP = 0xFFFFFFFF
+SEQCDC_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _u32, _u64, _i32, _p = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p
 
@@ -88,6 +89,7 @@ _SIGS = {
     "seqcdc_batch_destroy": ([_p], ctypes.c_int),
     "seqcdc_mark": ([_p, _u64, ctypes.POINTER(seqcdc_params), _p, _p], ctypes.c_int),
     "seqcdc_chunk_host": ([_p, _u64, ctypes.POINTER(seqcdc_params), _p, _u64, ctypes.POINTER(_u64)], ctypes.c_int),
+    "seqcdc_chunk_noalloc": ([_p, _u64, ctypes.POINTER(seqcdc_params), _p, _u64, _p, _p], ctypes.c_int),
     "seqcdc_dedup_stats": ([ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_u64), _u32,
                             ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_double),
                             ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
@@ -215,6 +217,13 @@ def seqcdc_chunk(d_stream, n, params, d_cuts, cap, stream=None, plan=None):
         raise err
     _check(rc)
     return cnt.value
+
+
+def seqcdc_chunk_noalloc(d_stream, n, params, d_cuts, cap, d_count, stream=None):
+    """Raw allocation-free call on device pointers: enqueues the chunking of n bytes on `stream`; the count goes to
+    the device uint64 at d_count (raises on argument errors, a stream too large for the fixed scratch included)."""
+    _check(lib.seqcdc_chunk_noalloc(d_stream, n, ctypes.byref(_as_params(params)), d_cuts, cap, d_count,
+                                    _stream_handle(stream)))
 
 
 _FILE_DTYPE = None
