@@ -92,9 +92,13 @@ int seqcdc_plan_set_tuning(seqcdc_plan* plan, uint64_t segment_bytes, uint32_t m
 int seqcdc_plan_get_tuning(seqcdc_plan* plan, uint64_t n, const seqcdc_params* p, uint64_t* segment_bytes,
                            uint32_t* mark_span_blocks, uint32_t* waves_per_cu);
 
-/* How a plan runs the resolve stage.  0 (the default): marking, pass A
- * (chains) and pass B (continuations) are separate launches.  All modes give
- * the same cuts. */
+/* How a plan runs the resolve stage.  0 (marked, the default): the mark
+ * kernel writes run-end and opposing bits for every input byte, then pass A
+ * (chains) and pass B (continuations) walk them.  1 (direct, skip-aware): no
+ * mark kernel; each chain loads the raw bytes of the 1 KiB windows it scans
+ * and computes their bits itself, so the sub-minimum region after every cut
+ * and the bytes a skip passes over are never read (Sec. III-B, III-C).
+ * Overlapped batches are marked-mode only.  All modes give the same cuts. */
 int seqcdc_plan_set_mode(seqcdc_plan* plan, int mode);
 
 /* Overlapped batches (mode 0 only): the files of a seqcdc_chunk_batch call
@@ -125,8 +129,8 @@ int seqcdc_plan_set_overlap(seqcdc_plan* plan, uint32_t groups);
 int seqcdc_plan_set_timing(seqcdc_plan* plan, int on);
 int seqcdc_plan_phase_ms(seqcdc_plan* plan, float* ms4);
 
-/* Autotuner: time candidate segment sizes, mark spans and resolve occupancies
- * on the given device-resident sample stream, and keep
+/* Autotuner: time candidate segment sizes, mark spans, resolve occupancies and
+ * both resolve modes on the given device-resident sample stream, and keep
  * the fastest in a process-wide cache keyed by (arch, CU count, seq_length,
  * average class), which plans consult for settings not set explicitly.
  * Results are exact for every choice; only speed differs.  *best_ms receives

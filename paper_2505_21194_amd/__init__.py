@@ -172,7 +172,8 @@ def seqcdc_plan_set_tuning(plan, segment_bytes=0, mark_span_blocks=0, waves_per_
 
 
 def seqcdc_plan_set_mode(plan, mode):
-    """Resolve mode: 0 = mark kernel, then pass A, pass B, stitch and compaction as separate launches (default)."""
+    """Resolve mode: 0 = marked (the mark kernel, then pass A, pass B, stitch and compaction; default); 1 = direct
+    (skip-aware chains that read only the raw windows they scan; no mark kernel)."""
     _check(lib.seqcdc_plan_set_mode(plan, mode))
 
 

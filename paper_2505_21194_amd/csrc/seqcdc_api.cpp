@@ -270,9 +270,12 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   // Overlapped batches take the files largest first and cut them into groups
   // of about equal bytes; everything below (spans, chains) is numbered in
   // that order, so each group owns a contiguous range of spans and chains.
+  // resolve mode: 0 = the mark kernel, then chains over its bits; 1 = direct
+  // (skip-aware) chains over the raw bytes, no mark kernel
+  const bool direct = !mark_only && pl->mode_for(specs[0].p) == 1;
   u64 total_n = 0;
   for (u32 f = 0; f < nfiles; f++) total_n += specs[f].n;
-  u32 G = mark_only ? 1 : pl->groups_for(nfiles, total_n);
+  u32 G = (mark_only || direct) ? 1 : pl->groups_for(nfiles, total_n);
   std::vector<u32> perm(nfiles);
   for (u32 f = 0; f < nfiles; f++) perm[f] = f;
   if (G > 1) std::stable_sort(perm.begin(), perm.end(), [&](u32 a, u32 b) { return specs[a].n > specs[b].n; });
@@ -374,8 +377,8 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
 
   // ---- device workspace
   int rc;
-  if ((rc = pl->eo.reserve(mark_only ? 256 : eo_bytes + 256))) return rc;
-  if ((rc = pl->esum.reserve(esum_bytes + 256))) return rc;
+  if ((rc = pl->eo.reserve((mark_only || direct) ? 256 : eo_bytes + 256))) return rc;
+  if ((rc = pl->esum.reserve(direct ? 256 : esum_bytes + 256))) return rc;
   if ((rc = pl->list.reserve(std::max<u64>(list_entries, 1) * 8))) return rc;
   if ((rc = pl->cont.reserve(std::max<u64>(cont_entries, 1) * 8))) return rc;
   const size_t chain_bytes = carve_size({nchains * 4ull, nchains * 8ull, nchains * 4ull, nchains * 4ull,
@@ -391,8 +394,13 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   const u64 nflags = 16ull * (G + 2);
   if ((rc = pl->flags.reserve(nflags * 4))) return rc;
 
-  // assign device pointers
+  // assign device pointers (direct chains read neither)
   for (u32 f = 0; f < nfiles; f++) {
+    if (direct) {
+      fd[f].eo = nullptr;
+      fd[f].esum = nullptr;
+      continue;
+    }
     if (!mark_only) fd[f].eo = (u32*)((char*)pl->eo.p + (uintptr_t)fd[f].eo);
     fd[f].esum = (uint8_t*)pl->esum.p + (uintptr_t)fd[f].esum;
   }
@@ -478,18 +486,18 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
     const u32 groups = std::max<u32>(1, pl->cus * waves / kWavesPerGroup);  // 4 independent waves each
     HIP_TRY(launch_clear(heads, 32, st));
     HIP_TRY(timing_mark(pl, 0, st));  // the mark phase is the mark kernel alone
-    HIP_TRY(launch_mark(d_files, d_hint, 0, spans, U, st));
+    if (!direct) HIP_TRY(launch_mark(d_files, d_hint, 0, spans, U, st));
     HIP_TRY(timing_mark(pl, 1, st));
     HIP_TRY(launch_chains(d_files, ws, (const u32*)dev(h_order), nchains, heads,
-                          std::min<u32>(groups, (nchains + 3) / 4), st));
+                          std::min<u32>(groups, (nchains + 3) / 4), direct, st));
     HIP_TRY(timing_mark(pl, 2, st));
     if (!multi.empty()) {
       const u32 nb = (u32)border.size();
       HIP_TRY(launch_continue(d_files, ws, (const u32*)dev(h_border), nb, heads + 16,
-                              std::max<u32>(1, std::min<u32>(groups, (nb + 3) / 4)), st));
+                              std::max<u32>(1, std::min<u32>(groups, (nb + 3) / 4)), direct, st));
       HIP_TRY(timing_mark(pl, 3, st));
       HIP_TRY(launch_stitch(d_files, ws, (const u32*)dev(h_multi), (u32)multi.size(), st));
-      HIP_TRY(launch_compact(d_files, ws, (const u32*)dev(h_compact), (u32)compact.size(), st));
+      HIP_TRY(launch_compact(d_files, ws, (const u32*)dev(h_compact), (u32)compact.size(), direct, st));
     } else {
       HIP_TRY(timing_mark(pl, 3, st));
     }
@@ -517,7 +525,7 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
       HIP_TRY(hipStreamWaitEvent(sa, pl->ev_mark[g], 0));
       const u32 lo = chain_at(gfile[g]), cnt = chain_at(gfile[g + 1]) - lo;
       HIP_TRY(launch_chains(d_files, ws, d_order + lo, cnt, heads + 16 * g,
-                            std::max<u32>(1, std::min<u32>(groups, (cnt + 3) / 4)), sa));
+                            std::max<u32>(1, std::min<u32>(groups, (cnt + 3) / 4)), false, sa));
       if (g == 0) HIP_TRY(hipEventRecord(pl->ev_chain_first, sa));
     }
     HIP_TRY(timing_mark(pl, 2, sa));
@@ -527,13 +535,13 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
       const u32 nb = (u32)border.size();
       HIP_TRY(hipStreamWaitEvent(sb, pl->ev_chain_first, 0));
       HIP_TRY(launch_continue(d_files, ws, d_border, border_first, heads + 16 * G,
-                              std::max<u32>(1, std::min<u32>(groups, (border_first + 3) / 4)), sb));
+                              std::max<u32>(1, std::min<u32>(groups, (border_first + 3) / 4)), false, sb));
       HIP_TRY(hipStreamWaitEvent(sb, pl->ev_chain_last, 0));
       HIP_TRY(launch_continue(d_files, ws, d_border + border_first, nb - border_first, heads + 16 * (G + 1),
-                              std::max<u32>(1, std::min<u32>(groups, (nb - border_first + 3) / 4)), sb));
+                              std::max<u32>(1, std::min<u32>(groups, (nb - border_first + 3) / 4)), false, sb));
       HIP_TRY(timing_mark(pl, 3, sb));
       HIP_TRY(launch_stitch(d_files, ws, (const u32*)dev(h_multi), (u32)multi.size(), sb));
-      HIP_TRY(launch_compact(d_files, ws, (const u32*)dev(h_compact), (u32)compact.size(), sb));
+      HIP_TRY(launch_compact(d_files, ws, (const u32*)dev(h_compact), (u32)compact.size(), false, sb));
     } else {
       HIP_TRY(hipStreamWaitEvent(sb, pl->ev_chain_last, 0));
       HIP_TRY(timing_mark(pl, 3, sb));
@@ -699,7 +707,7 @@ int seqcdc_plan_set_tuning(seqcdc_plan* plan, uint64_t segment_bytes, uint32_t m
 
 int seqcdc_plan_set_mode(seqcdc_plan* plan, int mode) {
   if (!plan) return fail(SEQCDC_EINVAL, "plan is NULL");
-  if (mode != 0) return fail(SEQCDC_EINVAL, "mode must be 0 (marked)");
+  if (mode != 0 && mode != 1) return fail(SEQCDC_EINVAL, "mode must be 0 (marked) or 1 (direct)");
   Plan* pl = (Plan*)plan;
   std::lock_guard<std::mutex> g(pl->mu);
   pl->mode = mode;

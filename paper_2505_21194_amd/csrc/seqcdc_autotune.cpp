@@ -1,6 +1,6 @@
 // Autotuner: picks the segment length of speculative resolution, the mark
-// span and the waves per CU of the persistent chain kernels by timing
-// candidates on a device-resident sample.  Every candidate produces the same
+// span, the waves per CU of the persistent chain kernels and the resolve mode
+// (marked or direct) by timing candidates on a device-resident sample.  Every candidate produces the same
 // cuts; only speed differs.  Results go to a process-wide cache keyed by
 // (arch, CU count, SeqLength, average class).
 #include <hip/hip_runtime.h>
@@ -91,6 +91,18 @@ extern "C" int seqcdc_autotune(seqcdc_plan* plan, const void* d_sample, uint64_t
     const u32 s = best.span_blocks;
     for (u32 w : {8u, 12u, 20u})
       if ((rc = trial(m, s, w))) break;
+  }
+  if (!rc) {  // the direct (skip-aware) chains: no mark span; segment length and occupancy
+    pl->mode = 1;
+    const u64 m0 = best.seg_mult;
+    const u32 s = best.span_blocks;
+    for (u64 m : {m0 / 2, m0, m0 * 2})
+      if (m >= 16 && (rc = trial(m, s, 12))) break;
+    if (!rc) {
+      const u64 m = best.mode == 1 ? best.seg_mult : m0;
+      for (u32 w : {8u, 16u})
+        if ((rc = trial(m, s, w))) break;
+    }
   }
   pl->mode = saved_mode;
   pl->seg_override = saved_seg;

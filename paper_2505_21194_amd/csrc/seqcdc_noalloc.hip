@@ -203,16 +203,17 @@ extern "C" int seqcdc_chunk_noalloc(const void* d_stream, uint64_t n, const seqc
   const u32 groups = cus * kNoAllocWaves / kWavesPerGroup;
   if ((e = launch_mark(d_files, (const u32*)(base + o_hint), 0, spans, kNoAllocSpanBlocks, st)) != hipSuccess)
     return hip_fail(e, "mark kernel");
-  if ((e = launch_chains(d_files, ws, iota, nseg, heads, std::min<u32>(groups, (nseg + 3) / 4), st)) != hipSuccess)
+  if ((e = launch_chains(d_files, ws, iota, nseg, heads, std::min<u32>(groups, (nseg + 3) / 4), false, st)) !=
+      hipSuccess)
     return hip_fail(e, "chains kernel");
   if (multi) {
     const u32 nb = nseg - 1;
     if ((e = launch_continue(d_files, ws, iota, nb, heads + 16, std::max<u32>(1, std::min<u32>(groups, (nb + 3) / 4)),
-                             st)) != hipSuccess)
+                             false, st)) != hipSuccess)
       return hip_fail(e, "continue kernel");
     if ((e = launch_stitch(d_files, ws, (const u32*)(base + o_multi), 1, st)) != hipSuccess)
       return hip_fail(e, "stitch kernel");
-    if ((e = launch_compact(d_files, ws, iota, nseg, st)) != hipSuccess) return hip_fail(e, "compact kernel");
+    if ((e = launch_compact(d_files, ws, iota, nseg, false, st)) != hipSuccess) return hip_fail(e, "compact kernel");
   }
   return SEQCDC_OK;
 }

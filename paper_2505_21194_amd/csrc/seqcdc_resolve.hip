@@ -21,12 +21,19 @@
 //
 // A chain is one wave, and the waves of a workgroup take chains
 // independently.  Its state is wave-uniform (scalar registers); the lanes
-// hold one sub-window of mark bits (4 KiB of input, one 64-byte group per
-// lane) with per-window prefix counts, so every scan step is a handful of lane
-// reads and scalar operations.  A per-1 KiB summary of run ends lets a chain
-// cross regions with no run end (zero runs, most short periodic patterns)
-// without reading their bits: with no run end before the limit, the chunk
-// ends at the limit whatever the opposing pairs do.
+// hold one window of run-end and opposing bits, one group of bytes per lane,
+// with per-window prefix counts, so every scan step is a handful of lane reads
+// and scalar operations.  Two kinds of window feed the same state machine:
+//  - marked (MarkedChain): 4 KiB of bits the mark kernel wrote (EO16), one
+//    64-byte group per lane.  A per-1 KiB summary of run ends lets a chain
+//    cross regions with no run end (zero runs, most short periodic patterns)
+//    without reading their bits: with no run end before the limit, the chunk
+//    ends at the limit whatever the opposing pairs do.
+//  - direct (DirectChain, skip-aware): 1 KiB of raw input bytes, one 16-byte
+//    group per lane, whose bits the chain computes itself when it enters the
+//    window.  There is no mark pass: only the windows a chain scans are read
+//    from HBM, so the sub-minimum region after each cut and the bytes a skip
+//    passes over are never loaded (Sec. III-B, III-C).
 
 #include <hip/hip_runtime.h>
 
@@ -75,7 +82,11 @@ __device__ __forceinline__ void unpack_group(const uint4& v, u64& E, u64& O) {
 // lanes.  Indices of 64-byte groups, 1 KiB blocks and 4 KiB sub-windows are
 // 32-bit (streams are shorter than 256 GiB) and chunk-relative offsets are
 // 32-bit (max_size <= 1 GiB), so the state fits the scalar register file.
-struct Chain {
+struct MarkedChain {
+  static constexpr u32 kWin = kSubBytes;  // bytes per window
+  static constexpr u32 kG = 64;           // bytes per lane group
+  static constexpr bool kSummary = true;  // has the run-end summary
+  typedef u64 Word;                       // E / O bits of one group
   const uint4* eo;    // EO16 groups of the file
   const uint8_t* esum;
   u64 n;
@@ -99,9 +110,10 @@ struct Chain {
 
 constexpr u32 kNone = 0xFFFFFFFFu;
 
-__device__ __forceinline__ bool skipping(const Chain& ch) { return ch.trig != kNoSkip; }
+template <class Ch>
+__device__ __forceinline__ bool skipping(const Ch& ch) { return ch.trig != kNoSkip; }
 
-__device__ __forceinline__ void chain_init(Chain& ch, const FileDesc& F, SEQCDC_LOCAL u32x4* win) {
+__device__ __forceinline__ void chain_init(MarkedChain& ch, const FileDesc& F, SEQCDC_LOCAL u32x4* win) {
   ch.win = win;
   ch.eo = (const uint4*)F.eo;
   ch.esum = F.esum;
@@ -128,7 +140,7 @@ __device__ __forceinline__ void chain_init(Chain& ch, const FileDesc& F, SEQCDC_
 // Starts the DMA of sub-window `sub` into its LDS slot (sub % kRing): lane l
 // copies group sub*64 + l.  Lanes past the end read the last group instead
 // (always in bounds); their data is discarded when the slot is read.
-__device__ __forceinline__ void dma_window(const Chain& ch, u32 sub) {
+__device__ __forceinline__ void dma_window(const MarkedChain& ch, u32 sub) {
   const u32 g = sub * 64u + lane_id();
   const u32 gs = g < ch.groups ? g : ch.groups - 1;
   __builtin_amdgcn_global_load_lds(as_global((const void*)(ch.eo + gs)), ch.win + (sub & (kRing - 1)) * 64, 16, 0,
@@ -142,7 +154,7 @@ __device__ __forceinline__ void dma_window(const Chain& ch, u32 sub) {
 // cut is usually a few hundred bytes away, and the scan after it starts
 // min_size - SeqLength bytes later).  Windows are entered in increasing
 // order, so the slots of the kRing - 1 windows after `sub` never collide.
-__device__ __forceinline__ void ensure(Chain& ch, u32 sub, u32 hint) {
+__device__ __forceinline__ void ensure(MarkedChain& ch, u32 sub, u32 hint) {
   if (ch.cur == sub) return;
   const u32 d = sub - ch.pf_base;
   u32 mask = d < kRing ? ch.pf_mask >> d : 0u;
@@ -183,7 +195,7 @@ __device__ __forceinline__ void ensure(Chain& ch, u32 sub, u32 hint) {
 // Extend the summary knowledge from block b by one load (up to 1024 blocks,
 // 1 MiB of input): afterwards blocks [b, sum_to) are known to hold no run
 // end.
-__device__ void summary_extend(Chain& ch, u32 b) {
+__device__ void summary_extend(MarkedChain& ch, u32 b) {
   const u32 lane = lane_id();
   const u32 nb = ch.nblocks;
   u32 to = b;
@@ -224,50 +236,238 @@ __device__ void summary_extend(Chain& ch, u32 b) {
 // True if no block in [b, ceil(L/1024)) holds a run end.  Uses and extends
 // the summary knowledge; cheap when it already covers b.  Block indices are
 // compared in 32 bits: sum_to * 1024 >= L exactly when sum_to >= ceil(L / 1024).
-__device__ __forceinline__ bool no_end_before(Chain& ch, u32 b, u64 L) {
+__device__ __forceinline__ bool no_end_before(MarkedChain& ch, u32 b, u64 L) {
   const u32 lb = (u32)((L + 1023) >> 10);
   if (!(ch.sum_from <= b && b <= ch.sum_to)) summary_extend(ch, b);
   while (!ch.sum_hit && ch.sum_to < lb) summary_extend(ch, ch.sum_to);
   return ch.sum_to >= lb;
 }
 
-// Opposing pairs of the window at positions < pos (0 <= pos <= 4096).
-__device__ __forceinline__ u32 opp_before(const Chain& ch, u32 pos) {
-  if (pos >= kSubBytes) return ch.total;
-  const u32 g = pos >> 6, b = pos & 63;
-  const u32 prior = readlane(ch.excl, g);
-  return b ? prior + (u32)__popcll(readlane64(ch.O, g) & ((1ull << b) - 1ull)) : prior;
+// ---------------------------------------------------------------------------
+// The direct (skip-aware) chain: raw 1 KiB windows, bits computed on entry
+// ---------------------------------------------------------------------------
+
+constexpr u32 kDirectWin = 1024;                 // input bytes per window: 64 lanes x 16
+constexpr u32 kDirectSlots = 8;                  // LDS window slots per wave
+constexpr u32 kDirectSlotChunks = 66;            // aligned 16-byte chunks per slot
+constexpr u32 kDirectLdsChunks = kDirectSlots * kDirectSlotChunks;
+
+// Slots hold the aligned 16-byte chunks 64w - 1 .. 64w + 64 of window w
+// (counted from the aligned address at or below the file's first byte): the
+// window's 1 KiB wherever it starts within a chunk, plus the 16 bytes before
+// it (the predecessors of lane 0's bytes).  Any slot holds any window; lane
+// i < kDirectSlots of `tag` names the window in slot i.  Windows are entered
+// in increasing order, so a slot holding a window below the current one is
+// free.  No fetch is ever issued into a slot whose earlier fetch may still be
+// in flight: prefetches are issued right after a wait for all earlier ones,
+// into slots that were free then; a window that was not prefetched goes into
+// the current window's slot, whose fetch completed before it was read; and a
+// new chain first waits for the fetches its wave left in flight.
+struct DirectChain {
+  static constexpr u32 kWin = kDirectWin;
+  static constexpr u32 kG = 16;
+  static constexpr bool kSummary = false;
+  typedef u32 Word;
+  const uint8_t* base;  // aligned address at or below the file's first byte
+  u64 last_chunk;       // chunks 0 .. last_chunk overlap the file (n > 0)
+  u64 n;
+  u32 nwin;             // ceil(n / 1024)
+  u32 r;                // first byte's offset in its chunk (0..15)
+  u32 down_is_fav;      // decreasing mode
+  u32 min_size, max_size, sl, trig, skip;
+  u32 cur;              // window whose bits are held (kNone = none)
+  u32 cur_slot;         // its slot
+  u32 tag;              // lane i < kDirectSlots: window held by slot i (kNone = empty)
+  SEQCDC_LOCAL u32x4* win;  // kDirectSlots slots of kDirectSlotChunks chunks
+  u32 E, O;             // lane l: bits of bytes 16l .. 16l+15 of the window (16 each)
+  u32 incl, excl, fe, total;
+  u64 emask;
+};
+
+__device__ __forceinline__ void chain_init(DirectChain& ch, const FileDesc& F, SEQCDC_LOCAL u32x4* win) {
+  const uintptr_t addr = (uintptr_t)F.data;
+  ch.r = (u32)(addr & 15);
+  ch.base = (const uint8_t*)(addr - ch.r);
+  ch.n = F.n;
+  ch.last_chunk = F.n ? (ch.r + F.n - 1) >> 4 : 0;
+  ch.nwin = (u32)((F.n + kDirectWin - 1) / kDirectWin);
+  ch.down_is_fav = F.mode;
+  ch.min_size = (u32)F.min_size;
+  ch.max_size = (u32)F.max_size;
+  ch.sl = F.sl;
+  ch.trig = F.trig;
+  ch.skip = F.skip;
+  ch.cur = kNone;
+  ch.cur_slot = 0;
+  ch.tag = kNone;
+  ch.win = win;
+  SEQCDC_WAIT_VMEM();  // fetches of the wave's previous chain
+  ch.E = ch.O = 0;
+  ch.incl = ch.excl = ch.total = 0;
+  ch.fe = 16;
+  ch.emask = 0;
 }
 
-// First admissible run end of the current sub-window at or after er (a
-// byte offset in the window, possibly >= kSubBytes), or kSubBytes if none.
-// Branch-free: the word of group er/64 and the first run end of the next
-// group holding one are both read, and the right one is selected.
-__device__ __forceinline__ u32 first_end(const Chain& ch, u32 er) {
-  const u32 ge = er < kSubBytes ? er >> 6 : 63u;
-  const u64 word = er < kSubBytes ? readlane64(ch.E, ge) & (~0ull << (er & 63)) : 0ull;
-  const u64 later = (er < kSubBytes && ge < 63) ? ch.emask & (~0ull << (ge + 1)) : 0ull;
+// Starts the DMA of window w into slot s: lane l copies chunk 64w - 1 + l into
+// slot chunk l, lanes 0 and 1 chunks 64w + 63 and 64w + 64 into slot chunks 64
+// and 65.  Chunks outside the file are clamped to its first or last chunk
+// (always in bounds: a 16-byte aligned chunk never straddles a page); bytes
+// outside the file are masked when the bits are computed.
+__device__ __forceinline__ void dma_raw(const DirectChain& ch, u32 w, u32 s) {
+  const u32 lane = lane_id();
+  SEQCDC_LOCAL u32x4* dst = ch.win + s * kDirectSlotChunks;
+  const u64 first = (u64)w * 64;  // chunk index of the window's slot chunk 1
+  const u64 g = first + lane;     // slot chunk `lane` is chunk g - 1
+  const u64 gm = g == 0 ? 0 : (g - 1 < ch.last_chunk ? g - 1 : ch.last_chunk);
+  __builtin_amdgcn_global_load_lds(as_global((const void*)(ch.base + 16 * gm)), dst, 16, 0, 0);
+  if (lane < 2) {
+    const u64 t = first + 63 + lane;
+    const u64 tm = t < ch.last_chunk ? t : ch.last_chunk;
+    __builtin_amdgcn_global_load_lds(as_global((const void*)(ch.base + 16 * tm)), dst + 64, 16, 0, 0);
+  }
+}
+
+// Slot holding window w, or kNone.
+__device__ __forceinline__ u32 slot_of(const DirectChain& ch, u32 w) {
+  const u64 m = ballot(lane_id() < kDirectSlots && ch.tag == w);
+  return m ? ctz64(m) : kNone;
+}
+
+// Starts fetching window w into a free slot if it is in the file, not held
+// and a slot is free (never the slot of window `keep`).
+__device__ __forceinline__ void prefetch_raw(DirectChain& ch, u32 w, u32 keep) {
+  if (w >= ch.nwin) return;
+  const u32 lane = lane_id();
+  const u64 held = ballot(lane < kDirectSlots && ch.tag == w);
+  const u64 free = ballot(lane < kDirectSlots && (ch.tag == kNone || ch.tag < keep));
+  if (held || !free) return;
+  const u32 s = ctz64(free);
+  dma_raw(ch, w, s);
+  if (lane == s) ch.tag = w;
+}
+
+// Loads window w and computes its bits and per-window facts.  On entry the
+// fetches of the windows the chain is likely to need next are started: the
+// next one (the scan continues) and the two from `hint` on, the window where
+// the scan would restart if a cut were found right at the current position (a
+// cut is usually a few hundred bytes away, and the scan after it starts
+// min_size - SeqLength bytes later).
+__device__ __forceinline__ void ensure(DirectChain& ch, u32 w, u32 hint) {
+  if (ch.cur == w) return;
+  const u32 lane = lane_id();
+  u32 s = slot_of(ch, w);
+  if (s == kNone) {  // not prefetched: into the slot of the window entered before (slot 0 in a new chain)
+    s = ch.cur_slot;
+    dma_raw(ch, w, s);
+    if (lane == s) ch.tag = w;
+  }
+  ch.cur_slot = s;
+  SEQCDC_WAIT_VMEM();
+  // lane l's 16 bytes and the 16 before them: slot bytes r + 16l .. r + 16l + 31,
+  // read as 9 aligned dwords and realigned
+  const SEQCDC_LOCAL u32* sw = (const SEQCDC_LOCAL u32*)(ch.win + s * kDirectSlotChunks);
+  const u32 d0 = (ch.r + 16 * lane) >> 2, sh = ch.r & 3;
+  u32 dw[9];
+#pragma unroll
+  for (int k = 0; k < 9; k++) dw[k] = sw[d0 + k];
+  u32 halo[4], x[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    halo[k] = __builtin_amdgcn_alignbyte(dw[k + 1], dw[k], sh);
+    x[k] = __builtin_amdgcn_alignbyte(dw[k + 5], dw[k + 4], sh);
+  }
+  // the next fetches go to other slots while the bits are computed
+  prefetch_raw(ch, w + 1, w);
+  prefetch_raw(ch, hint, w);
+  prefetch_raw(ch, hint + 1, w);
+  // Sec. III-D: favourable / opposing pairs, then run ends of SeqLength bytes
+  u32 up, dn, hup, hdn;
+  compare16(x, halo[3] >> 24, up, dn);
+  compare16(halo, 0u, hup, hdn);  // only bits 2..15 are used (for lane 0's runs)
+  u32 fav = ch.down_is_fav ? dn : up;
+  u32 opp = ch.down_is_fav ? up : dn;
+  const u32 hfav = readlane(ch.down_is_fav ? hdn : hup, 0);
+  const u64 q0 = (u64)w * kDirectWin + 16 * lane;
+  if (q0 == 0) {  // byte 0 has no predecessor
+    fav &= ~1u;
+    opp &= ~1u;
+  }
+  u32 keep = 0xFFFFu;  // bytes of the file
+  if (q0 >= ch.n) keep = 0;
+  else if (ch.n - q0 < 16) keep = (1u << (u32)(ch.n - q0)) - 1u;
+  const u32 e = run_ends16(fav, shift_up_lanes(fav, hfav), ch.sl - 1) & keep;
+  ch.E = e;
+  ch.O = opp & keep;
+  ch.cur = w;
+  ch.emask = ballot(e != 0);
+  ch.fe = e ? (u32)__builtin_ctz(e) : 16u;
+  if (skipping(ch)) {
+    const u32 cnt = (u32)__popc(ch.O);
+    ch.incl = wave_incl_scan(cnt);
+    ch.excl = ch.incl - cnt;
+    ch.total = readlane(ch.incl, 63);
+  }
+}
+
+// Group words: one lane's E or O bits.
+__device__ __forceinline__ u32 read_group(u32 v, u32 g) { return readlane(v, g); }
+__device__ __forceinline__ u64 read_group(u64 v, u32 g) { return readlane64(v, g); }
+__device__ __forceinline__ u32 popcount(u32 v) { return (u32)__popc(v); }
+__device__ __forceinline__ u32 popcount(u64 v) { return (u32)__popcll(v); }
+__device__ __forceinline__ u32 lowest_bit(u32 v) { return (u32)__builtin_ctz(v); }
+__device__ __forceinline__ u32 lowest_bit(u64 v) { return ctz64(v); }
+
+template <u32 G>
+struct GroupShift {
+  static constexpr u32 value = G == 64 ? 6 : G == 16 ? 4 : 0;
+  static_assert(value != 0, "groups are 16 or 64 bytes");
+};
+
+// Opposing pairs of the window at positions < pos (0 <= pos <= kWin).
+template <class Ch>
+__device__ __forceinline__ u32 opp_before(const Ch& ch, u32 pos) {
+  typedef typename Ch::Word W;
+  if (pos >= Ch::kWin) return ch.total;
+  const u32 g = pos >> GroupShift<Ch::kG>::value, b = pos & (Ch::kG - 1);
+  const u32 prior = readlane(ch.excl, g);
+  return b ? prior + popcount(read_group(ch.O, g) & ((W(1) << b) - W(1))) : prior;
+}
+
+// First admissible run end of the current window at or after er (a byte
+// offset in the window, possibly >= kWin), or kWin if none.  Branch-free: the
+// word of group er/kG and the first run end of the next group holding one are
+// both read, and the right one is selected.
+template <class Ch>
+__device__ __forceinline__ u32 first_end(const Ch& ch, u32 er) {
+  typedef typename Ch::Word W;
+  constexpr u32 kWin = Ch::kWin, kG = Ch::kG;
+  const u32 ge = er < kWin ? er >> GroupShift<kG>::value : 63u;
+  const W word = er < kWin ? read_group(ch.E, ge) & (~W(0) << (er & (kG - 1))) : W(0);
+  const u64 later = (er < kWin && ge < 63) ? ch.emask & (~0ull << (ge + 1)) : 0ull;
   const u32 g2 = later ? ctz64(later) : 63u;
   const u32 f2 = readlane(ch.fe, g2);
-  return word ? ge * 64u + ctz64(word) : (later ? g2 * 64u + f2 : kSubBytes);
+  return word ? ge * kG + lowest_bit(word) : (later ? g2 * kG + f2 : kWin);
 }
 
-// Position in the current sub-window of the need-th opposing pair at or after
-// pr, or kSubBytes if the window holds fewer (then *left = pairs it holds at
-// or after pr).  The trigger is in the first group whose inclusive count
+// Position in the current window of the need-th opposing pair at or after
+// pr, or kWin if the window holds fewer (then *left = pairs it holds at or
+// after pr).  The trigger is in the first group whose inclusive count
 // reaches (pairs before pr) + need, at the right set bit of that group.
-__device__ __forceinline__ u32 nth_opposing(const Chain& ch, u32 pr, u32 need, u32& left) {
+template <class Ch>
+__device__ __forceinline__ u32 nth_opposing(const Ch& ch, u32 pr, u32 need, u32& left) {
   const u32 base = opp_before(ch, pr);
   left = ch.total - base;
-  if (need > left) return kSubBytes;
+  if (need > left) return Ch::kWin;
   const u32 target = base + need;
   const u32 gt = ctz64(ballot(ch.incl >= target));
-  return gt * 64u + select_bit(readlane64(ch.O, gt), target - readlane(ch.excl, gt));
+  return gt * Ch::kG + select_bit((u64)read_group(ch.O, gt), target - readlane(ch.excl, gt));
 }
 
 // The cut that follows a cut (or a speculative start) at c.  Wave-uniform.
 // Offsets inside the chunk are 32-bit, relative to c (max_size <= 1 GiB).
-__device__ u64 next_cut(Chain& ch, u64 c) {
+template <class Ch>
+__device__ u64 next_cut(Ch& ch, u64 c) {
+  constexpr u32 kWin = Ch::kWin;
   // rem = n - c, tested on its 32-bit halves (scalar compares): c >= n makes
   // it zero or wrap to a huge value (the top bit set, as streams are shorter
   // than 2^63 bytes)
@@ -281,43 +481,47 @@ __device__ u64 next_cut(Chain& ch, u64 c) {
   const u32 c32 = (u32)c;
   for (;;) {
     if (p >= lim) return c + lim;
-    if (ch.hot) {  // inside a stretch known to hold no run end: nothing to find before the limit?
-      const u32 e_lo = s + ch.sl - 1;
-      const u32 b = (u32)((c + (e_lo > p ? e_lo : p)) >> 10);
-      if (ch.sum_from <= b && b <= ch.sum_to) {
-        if (no_end_before(ch, b, c + lim)) return c + lim;
-      } else {
-        ch.hot = false;
+    if constexpr (Ch::kSummary) {
+      if (ch.hot) {  // inside a stretch known to hold no run end: nothing to find before the limit?
+        const u32 e_lo = s + ch.sl - 1;
+        const u32 b = (u32)((c + (e_lo > p ? e_lo : p)) >> 10);
+        if (ch.sum_from <= b && b <= ch.sum_to) {
+          if (no_end_before(ch, b, c + lim)) return c + lim;
+        } else {
+          ch.hot = false;
+        }
       }
     }
-    const u32 sub = (u32)((c + p) / kSubBytes);
-    ensure(ch, sub, (u32)((c + p + ch.min_size - ch.sl) / kSubBytes));
-    const u32 w = sub * kSubBytes - c32;  // window start relative to c (mod 2^32)
-    const u32 lw = lim - w < kSubBytes ? lim - w : kSubBytes;  // scan limit inside this window
+    const u32 sub = (u32)((c + p) / kWin);
+    ensure(ch, sub, (u32)((c + p + ch.min_size - ch.sl) / kWin));
+    const u32 w = sub * kWin - c32;  // window start relative to c (mod 2^32)
+    const u32 lw = lim - w < kWin ? lim - w : kWin;  // scan limit inside this window
     // events inside this window; a skip that lands in it continues here
     for (;;) {
       const u32 e_lo = s + ch.sl - 1;  // earliest admissible run end
       const u32 qe = first_end(ch, (e_lo > p ? e_lo : p) - w);
-      u32 pt = kSubBytes, left = 0;
+      u32 pt = kWin, left = 0;
       if (skipping(ch)) pt = nth_opposing(ch, p - w, need, left);
       if (qe < pt) {
         if (qe < lw) return c + (u32)(w + qe) + 1;  // Sec. III-A: boundary just past the run (w may wrap)
         return c + lim;                      // nothing before the limit
       }
-      if (pt < kSubBytes) {  // Sec. III-C: skip SkipSize bytes after the trigger byte
+      if (pt < kWin) {  // Sec. III-C: skip SkipSize bytes after the trigger byte
         if (pt >= lw) return c + lim;
         const u32 rel = w + pt + 1;  // just past the trigger, relative to c: rel <= lim as pt < lw
         if (ch.skip >= lim - rel) return c + lim;  // the scan would restart at or past the limit
         s = rel + ch.skip;
         p = s + 1;
         need = ch.trig;
-        if (p - w < kSubBytes) continue;  // the scan resumes in this window
+        if (p - w < kWin) continue;  // the scan resumes in this window
         break;
       }
       need -= left;  // no event in this window
-      p = w + kSubBytes;
+      p = w + kWin;
       if (p >= lim) return c + lim;
-      if (no_end_before(ch, (u32)((c + p) >> 10), c + lim)) return c + lim;  // no run end before the limit
+      if constexpr (Ch::kSummary) {
+        if (no_end_before(ch, (u32)((c + p) >> 10), c + lim)) return c + lim;  // no run end before the limit
+      }
       break;
     }
   }
@@ -330,6 +534,7 @@ __device__ u64 next_cut(Chain& ch, u64 c) {
 // Pass A of one chain: cuts from its segment start (taken as a cut) until the
 // first cut at or past the segment end.  A single-segment file writes its
 // output directly; otherwise the cuts, exit cut last, go to the chain's list.
+template <class Ch>
 __device__ __forceinline__ void run_pass_a(const FileDesc* __restrict__ files, const ChainWs& ws, u32 chain,
                                            SEQCDC_LOCAL u32x4* win) {
   const u32 lane = lane_id();
@@ -340,7 +545,7 @@ __device__ __forceinline__ void run_pass_a(const FileDesc* __restrict__ files, c
   const bool direct = F.nseg == 1;
   u64 cnt = 0;
   if (F.n) {
-    Chain ch;
+    Ch ch;
     chain_init(ch, F, win);
     SEQCDC_GLOBAL u64* dst = as_global(direct ? F.out : ws.list + ws.list_off[chain]);
     const u64 cap = direct ? F.out_cap : ~0ull;
@@ -396,6 +601,7 @@ __device__ __forceinline__ i32 cursor_find(ListCursor& lc, u64 x) {
 // them already stored, until one is also a cut of the chain that owns that
 // position (or that chain's segment start).  Starts at the exit cut with
 // cc = 0.
+template <class Ch>
 __device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ files, const ChainWs& ws, u32 chain,
                                                  SEQCDC_LOCAL u32x4* win, u64 x, u32 cc) {
   const FileDesc& F = files[ws.chain_file[chain]];
@@ -419,7 +625,7 @@ __device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ fi
     u32 m = (u32)min64(x / F.seg, nseg - 1);
     u64 Sm = (u64)m * F.seg;                          // start of chain m's segment
     u64 m_end = m + 1 < nseg ? Sm + F.seg : ~0ull;    // start of the next one (none after the last)
-    Chain ch;
+    Ch ch;
     chain_init(ch, F, win);
     ListCursor lc;
     auto open = [&](u32 seg) {
@@ -470,28 +676,42 @@ __device__ __forceinline__ u64 exit_cut(const ChainWs& ws, u32 chain) {
 // Pass A over the chains in `order` (largest segments first), one wave per
 // chain; waves take chains from an atomic counter, independently of the other
 // waves of their workgroup.
+// LDS window slots of one wave.
+template <class Ch>
+struct WaveLds;
+template <>
+struct WaveLds<MarkedChain> {
+  static constexpr u32 kChunks = kRing * 64;
+};
+template <>
+struct WaveLds<DirectChain> {
+  static constexpr u32 kChunks = kDirectLdsChunks;
+};
+
+template <class Ch>
 __global__ __launch_bounds__(256) void chains_kernel(const FileDesc* __restrict__ files, ChainWs ws,
                                                      const u32* __restrict__ order, u32 nitems, u32* head) {
-  __shared__ u32x4 win[kWavesPerGroup][kRing * 64];
+  __shared__ u32x4 win[kWavesPerGroup][WaveLds<Ch>::kChunks];
   SEQCDC_LOCAL u32x4* mine = (SEQCDC_LOCAL u32x4*)win[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
   for (;;) {
     const u32 t = wave_pop(head);
     if (t >= nitems) return;
-    run_pass_a(files, ws, order[t], mine);
+    run_pass_a<Ch>(files, ws, order[t], mine);
   }
 }
 
 // Pass B over the chains in `order` (every chain but the last of each
 // multi-segment file).
+template <class Ch>
 __global__ __launch_bounds__(256) void continue_kernel(const FileDesc* __restrict__ files, ChainWs ws,
                                                        const u32* __restrict__ order, u32 nitems, u32* head) {
-  __shared__ u32x4 win[kWavesPerGroup][kRing * 64];
+  __shared__ u32x4 win[kWavesPerGroup][WaveLds<Ch>::kChunks];
   SEQCDC_LOCAL u32x4* mine = (SEQCDC_LOCAL u32x4*)win[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
   for (;;) {
     const u32 t = wave_pop(head);
     if (t >= nitems) return;
     const u32 chain = order[t];
-    run_continuation(files, ws, chain, mine, exit_cut(ws, chain), 0);
+    run_continuation<Ch>(files, ws, chain, mine, exit_cut(ws, chain), 0);
   }
 }
 
@@ -707,10 +927,11 @@ __global__ __launch_bounds__(kStitchThreads) void stitch_kernel(const FileDesc* 
 
 // Compaction: one wave per chain of a multi-segment file copies its exact
 // part; a continuation longer than its buffer is regenerated by walking on.
+template <class Ch>
 __global__ __launch_bounds__(256) void compact_kernel(const FileDesc* __restrict__ files, ChainWs ws,
                                                       const u32* __restrict__ chains, u32 nchains) {
   const u32 lane = lane_id();
-  __shared__ u32x4 win[kWavesPerGroup][kRing * 64];
+  __shared__ u32x4 win[kWavesPerGroup][WaveLds<Ch>::kChunks];
   const u32 w = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6));  // wave-uniform
   if (w >= nchains) return;
   const u32 chain = chains[w];
@@ -743,7 +964,7 @@ __global__ __launch_bounds__(256) void compact_kernel(const FileDesc* __restrict
       o += (stored - i < 64) ? stored - i : 64;
     }
     if (cc > stored) {
-      Chain ch;
+      Ch ch;
       chain_init(ch, F, (SEQCDC_LOCAL u32x4*)win[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
       u64 x = cont[stored - 1];
       for (u32 i = stored; i < cc; i++) {
@@ -770,16 +991,24 @@ hipError_t launch_clear(u32* p, u64 count, hipStream_t st) {
 }
 
 hipError_t launch_chains(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32* head,
-                         u32 groups, hipStream_t st) {
+                         u32 groups, bool direct, hipStream_t st) {
   if (!nitems) return hipSuccess;
-  hipLaunchKernelGGL(chains_kernel, dim3(groups), dim3(256), 0, st, d_files, ws, d_order, nitems, head);
+  if (direct)
+    hipLaunchKernelGGL(chains_kernel<DirectChain>, dim3(groups), dim3(256), 0, st, d_files, ws, d_order, nitems, head);
+  else
+    hipLaunchKernelGGL(chains_kernel<MarkedChain>, dim3(groups), dim3(256), 0, st, d_files, ws, d_order, nitems, head);
   return hipGetLastError();
 }
 
 hipError_t launch_continue(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32* head,
-                           u32 groups, hipStream_t st) {
+                           u32 groups, bool direct, hipStream_t st) {
   if (!nitems) return hipSuccess;
-  hipLaunchKernelGGL(continue_kernel, dim3(groups), dim3(256), 0, st, d_files, ws, d_order, nitems, head);
+  if (direct)
+    hipLaunchKernelGGL(continue_kernel<DirectChain>, dim3(groups), dim3(256), 0, st, d_files, ws, d_order, nitems,
+                       head);
+  else
+    hipLaunchKernelGGL(continue_kernel<MarkedChain>, dim3(groups), dim3(256), 0, st, d_files, ws, d_order, nitems,
+                       head);
   return hipGetLastError();
 }
 
@@ -789,11 +1018,14 @@ hipError_t launch_stitch(const FileDesc* d_files, const ChainWs& ws, const u32* 
   return hipGetLastError();
 }
 
-hipError_t launch_compact(const FileDesc* d_files, const ChainWs& ws, const u32* d_chains, u32 nchains,
+hipError_t launch_compact(const FileDesc* d_files, const ChainWs& ws, const u32* d_chains, u32 nchains, bool direct,
                           hipStream_t st) {
   if (!nchains) return hipSuccess;
   const u32 groups = (nchains + kWavesPerGroup - 1) / kWavesPerGroup;
-  hipLaunchKernelGGL(compact_kernel, dim3(groups), dim3(256), 0, st, d_files, ws, d_chains, nchains);
+  if (direct)
+    hipLaunchKernelGGL(compact_kernel<DirectChain>, dim3(groups), dim3(256), 0, st, d_files, ws, d_chains, nchains);
+  else
+    hipLaunchKernelGGL(compact_kernel<MarkedChain>, dim3(groups), dim3(256), 0, st, d_files, ws, d_chains, nchains);
   return hipGetLastError();
 }
 

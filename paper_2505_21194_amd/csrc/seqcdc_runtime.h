@@ -66,7 +66,7 @@ struct Plan {
   u32 last_nchains = 0, last_multi = 0;
   u64 seg_override = 0;
   u32 span_override = 0, waves_override = 0;
-  int mode = -1;  // resolve mode (0: marked); -1: tuned (else 0)
+  int mode = -1;  // resolve mode (0: marked, 1: direct); -1: tuned (else 0)
   // optional per-phase timing of the last call: events before the mark
   // kernel and after the mark, pass A, pass B and stitch + compaction
   bool timing = false, timed = false;

@@ -8,6 +8,7 @@
 * 512 MiB uniform in 64 KiB segments: more covered ranges than the stitch keeps in LDS.
 * 4096 files with log-normal sizes (median 256 KiB, sigma 1.5, 4 KiB..64 MiB), each a mixed stream of its own
   seed, at a 16 KiB average: the eager batched call and its prepared hipGraph replay.
+The plain streams and the 4096-file batch also run in the direct (skip-aware) resolve mode.
 """
 import numpy as np
 import pytest
@@ -30,6 +31,15 @@ def _say(*a):
     print("[case]", *a, flush=True)
 
 
+@pytest.fixture(scope="module")
+def direct_plan(env):
+    torch, seq = env
+    plan = seq.seqcdc_plan_create()
+    seq.seqcdc_plan_set_mode(plan, 1)
+    yield plan
+    seq.seqcdc_plan_destroy(plan)
+
+
 def _pd(p):
     return dict(mode=p.mode, seq_length=p.seq_length, min_size=p.min_size, max_size=p.max_size,
                 skip_trigger=p.skip_trigger, skip_size=p.skip_size)
@@ -44,19 +54,20 @@ def stream_1g(env):
 
 @pytest.mark.parametrize("avg_kib", [8, 16, 32])
 @pytest.mark.parametrize("mode", [0, 1])
-def test_plain_1gib_mixed(env, stream_1g, avg_kib, mode):
+def test_plain_1gib_mixed(env, stream_1g, direct_plan, avg_kib, mode):
     torch, seq = env
     host, dev = stream_1g
     p = seq.seqcdc_params_for_avg(avg_kib << 10)
     p.mode = mode
-    _say("plain 1 GiB mixed, avg", avg_kib, "KiB, mode", mode)
-    got = seq.chunk(dev, p).cpu().numpy().astype(np.uint64)
     want = oracle.chunk(host, **_pd(p))
-    assert got.size == want.size and np.array_equal(got, want)
+    for pl, label in ((None, "marked"), (direct_plan, "direct")):
+        _say("plain 1 GiB mixed, avg", avg_kib, "KiB, mode", mode, label)
+        got = seq.chunk(dev, p, plan=pl).cpu().numpy().astype(np.uint64)
+        assert got.size == want.size and np.array_equal(got, want), label
 
 
 @pytest.mark.parametrize("mode", [0, 1])
-def test_plain_1gib_mixed_seqlength6(env, stream_1g, mode):
+def test_plain_1gib_mixed_seqlength6(env, stream_1g, direct_plan, mode):
     """SeqLength counted as bytes with 6 in place of Table I's 5 (the reading under which Table I's averages hold
     on random data), 8 KiB parameters otherwise: many more skips per chunk and max-size cuts."""
     torch, seq = env
@@ -64,13 +75,14 @@ def test_plain_1gib_mixed_seqlength6(env, stream_1g, mode):
     p = seq.seqcdc_params_for_avg(8192)
     p.seq_length = 6
     p.mode = mode
-    _say("plain 1 GiB mixed, SeqLength 6, mode", mode)
-    got = seq.chunk(dev, p).cpu().numpy().astype(np.uint64)
     want = oracle.chunk(host, **_pd(p))
-    assert got.size == want.size and np.array_equal(got, want)
+    for pl, label in ((None, "marked"), (direct_plan, "direct")):
+        _say("plain 1 GiB mixed, SeqLength 6, mode", mode, label)
+        got = seq.chunk(dev, p, plan=pl).cpu().numpy().astype(np.uint64)
+        assert got.size == want.size and np.array_equal(got, want), label
 
 
-@pytest.mark.parametrize("mode", [0])
+@pytest.mark.parametrize("mode", [0, 1])
 def test_many_covered_ranges_512mib(env, mode):
     """512 MiB uniform at an 8 KiB average in the smallest segments (64 KiB): about half the 8192 boundaries
     jump a whole segment, and the active jumps (covered ranges) outnumber the 1024 the stitch keeps in LDS
@@ -115,7 +127,7 @@ def test_snapshot_series_full(env, snapshots, avg_kib):
     assert got[2] == pytest.approx(ref[2], abs=1e-12) and got[3] == pytest.approx(ref[3], rel=1e-12)
 
 
-def test_batched_4096_files(env):
+def test_batched_4096_files(env, direct_plan):
     torch, seq = env
     nfiles = 4096
     sizes = synth.lognormal_sizes(nfiles, 256 * 1024, 1.5, 4096, 64 << 20, seed=4).astype(np.int64)
@@ -144,6 +156,11 @@ def test_batched_4096_files(env):
     _say("batched 4096 files, eager")
     seq.seqcdc_chunk_batch(ftab, [p], cuts.data_ptr(), cut_offs, counts.data_ptr())
     check("eager")
+    cuts.zero_()
+    counts.zero_()
+    _say("batched 4096 files, eager, direct mode")
+    seq.seqcdc_chunk_batch(ftab, [p], cuts.data_ptr(), cut_offs, counts.data_ptr(), plan=direct_plan)
+    check("eager-direct")
     cuts.zero_()
     counts.zero_()
     _say("batched 4096 files, prepared graph")

@@ -14,7 +14,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-MODES = [0]  # resolve modes of seqcdc_plan_set_mode
+MODES = [0, 1]  # resolve modes of seqcdc_plan_set_mode: marked, direct
 
 
 @pytest.fixture(scope="module")

@@ -2,7 +2,9 @@
 
 Covers the mark bitmaps (Sec. III-D masks), the plain chunking path with speculative segments,
 stitching and compaction, forced tiny segments and non-converging (periodic / zero-run) data,
-ragged and tiny lengths, misaligned inputs, capacity errors and the batched path.
+ragged and tiny lengths, misaligned inputs, capacity errors and the batched path.  Every chunking
+check runs in both resolve modes: marked (the mark kernel's bits) and direct (skip-aware chains over
+raw windows).
 """
 import ctypes
 
@@ -28,6 +30,21 @@ def _say(*a):
     print("[case]", *a, flush=True)
 
 
+_DIRECT = {}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _direct_default(env):
+    """A plan in the direct resolve mode with default tuning, for the second run of every check."""
+    torch, seq = env
+    plan = seq.seqcdc_plan_create()
+    seq.seqcdc_plan_set_mode(plan, 1)
+    _DIRECT["plan"] = plan
+    yield
+    _DIRECT.clear()
+    seq.seqcdc_plan_destroy(plan)
+
+
 def _dev(torch, a, offset=0):
     """Device copy of a uint8 numpy array, starting `offset` bytes into a larger allocation."""
     if offset == 0:
@@ -48,11 +65,16 @@ def _gpu_cuts(env, data, params, plan=None, offset=0):
 
 
 def _check(env, data, params, plan=None, offset=0, label=""):
-    _say(label, "n=%d" % data.size, params, "offset=%d" % offset)
+    """The oracle's cuts from the default plan and a direct-mode plan (plan None), from each plan of a list, or
+    from one plan."""
     want = oracle.chunk(data, **params)
-    got = _gpu_cuts(env, data, params, plan=plan, offset=offset)
-    assert got.size == want.size and np.array_equal(got, want), \
-        (label, got.size, want.size, np.flatnonzero(got[:min(got.size, want.size)] != want[:min(got.size, want.size)])[:5])
+    plans = list(plan) if isinstance(plan, (list, tuple)) else ([None, _DIRECT["plan"]] if plan is None else [plan])
+    for k, pl in enumerate(plans):
+        _say(label, "plan", k, "n=%d" % data.size, params, "offset=%d" % offset)
+        got = _gpu_cuts(env, data, params, plan=pl, offset=offset)
+        assert got.size == want.size and np.array_equal(got, want), \
+            (label, k, got.size, want.size,
+             np.flatnonzero(got[:min(got.size, want.size)] != want[:min(got.size, want.size)])[:5])
 
 
 def P(mode=0, sl=5, mn=4096, mx=16384, trig=50, skip=256):
@@ -99,11 +121,17 @@ def test_mixed_32mib(env, avg, mode, sl):
 
 @pytest.fixture
 def tiny_plan(env):
+    """64 KiB segments, in the marked and the direct resolve mode."""
     torch, seq = env
-    plan = seq.seqcdc_plan_create()
-    seq.seqcdc_plan_set_tuning(plan, segment_bytes=64 * 1024)
-    yield plan
-    seq.seqcdc_plan_destroy(plan)
+    plans = []
+    for mode in (0, 1):
+        plan = seq.seqcdc_plan_create()
+        seq.seqcdc_plan_set_tuning(plan, segment_bytes=64 * 1024)
+        seq.seqcdc_plan_set_mode(plan, mode)
+        plans.append(plan)
+    yield plans
+    for plan in plans:
+        seq.seqcdc_plan_destroy(plan)
 
 
 @pytest.mark.parametrize("gen", ["uniform", "mixed"])
@@ -210,9 +238,10 @@ def test_chunk_host_convenience(env, n):
 
 def test_determinism_repeated(env, tiny_plan):
     data = synth.mixed(8 << 20, seed=123)
-    first = _gpu_cuts(env, data, P(), plan=tiny_plan)
+    first = _gpu_cuts(env, data, P(), plan=tiny_plan[0])
     for _ in range(5):
-        assert np.array_equal(_gpu_cuts(env, data, P(), plan=tiny_plan), first)
+        for pl in tiny_plan:
+            assert np.array_equal(_gpu_cuts(env, data, P(), plan=pl), first)
 
 
 def test_one_plan_alternating_layouts_and_rewritten_input(env):
@@ -241,14 +270,16 @@ def test_one_plan_alternating_layouts_and_rewritten_input(env):
 
 
 # ------------------------------------------------------------------ batched path
+@pytest.mark.parametrize("rmode", [0, 1])
 @pytest.mark.parametrize("seed", [0, 1])
-def test_batch_matches_oracle(env, seed):
+def test_batch_matches_oracle(env, seed, rmode):
     torch, seq = env
     rng = np.random.default_rng(seed)
     sizes = [int(x) for x in rng.integers(0, 3 << 20, 120)] + [0, 1, 64, 1023, 5000, 9 << 20]
     params = [P(), P(mode=1, sl=6, mn=8192, mx=32768, skip=512), P(sl=3, mn=64, mx=1024, trig=9, skip=40)]
     plan = seq.seqcdc_plan_create()
     seq.seqcdc_plan_set_tuning(plan, segment_bytes=256 * 1024)
+    seq.seqcdc_plan_set_mode(plan, rmode)
     try:
         datas = [synth.mixed(s, seed=1000 * seed + i) for i, s in enumerate(sizes)]
         pidx = [i % len(params) for i in range(len(sizes))]
