@@ -32,6 +32,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
 METRIC = "chunking GB/s on 1 MI355X (batched vs plain) + % HBM peak; p99 request latency"
+PROBE_STEPS = 6  # chunking steps of a whole-step traffic probe (each launches the step's kernels once)
+STEP_TRAFFIC = {"plain": os.path.join(HERE, "profiles", "step_traffic_plain1GiB.json"),
+                "batched": os.path.join(HERE, "profiles", "step_traffic_batched4096.json"),
+                "batched_direct": os.path.join(HERE, "profiles", "step_traffic_batched4096_direct.json")}
 
 
 def parse():
@@ -46,8 +50,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the library's autotuner (default settings)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="oracle work to time on the host")
-    ap.add_argument("--traffic-probe", action="store_true",
-                    help="only run a 1 GiB device copy and the mark kernel (for rocprofv3 --pmc runs)")
+    ap.add_argument("--traffic-probe", choices=["mark", "plain", "batched"], default=None,
+                    help="for rocprofv3 --pmc runs: a 1 GiB device copy (the calibration kernel), then only the mark "
+                         "kernel, or PROBE_STEPS whole plain or batched steps (default settings, no autotuning)")
+    ap.add_argument("--mode", type=int, default=None, help="resolve mode of the probe's plan (0 marked, 1 direct)")
     ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "mark_traffic.json"))
     return ap.parse_args()
 
@@ -78,16 +84,48 @@ def mark_roofline(n, kernel_ms, traffic_json):
             "kernel_ms": round(ms, 4), "alg_bytes_per_launch": alg}
 
 
-def batched(seq, torch, stream, plan, steps, warmup, dev, tune):
+def stored_step_traffic(key):
+    """HBM bytes per step from the committed whole-step counter summary, if it was taken on the current sources."""
+    try:
+        from paper_2505_21194_amd import profiling
+        t = json.load(open(STEP_TRAFFIC[key]))
+        if t.get("source_sha256") == profiling.all_sources_digest():
+            return round(t["bytes_per_step"])
+    except Exception:
+        pass
+    return None
+
+
+def step_roofline(alg_bytes, ms, traffic):
+    """Roofline of a whole step: algorithmic bytes and (when measured on these sources) counter bytes per step, over
+    the step's time."""
+    out = {"bound": "hbm", "alg_bytes": int(alg_bytes), "achieved": round(alg_bytes / (ms * 1e-3) / 1e9, 1),
+           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "traffic": traffic}
+    if traffic:
+        out["traffic_frac"] = round(traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return out
+
+
+def mark_alg_bytes(n):
+    """Algorithmic bytes of marking n bytes: read every byte, write 2 bits per byte (EO16) and one summary byte per
+    1 KiB block."""
+    return n + 16 * ((n + 63) // 64) + (n + 1023) // 1024
+
+
+def batch_workload(seq, torch, dev):
+    """The 4096-file batch: device bytes, sizes, parameters, output arrays and marshalled tables."""
     import synth
     nfiles = 4096
     sizes = synth.lognormal_sizes(nfiles, 256 * 1024, 1.5, 4096, 64 << 20, seed=4).astype(np.int64)
     total = int(sizes.sum())
     log("batched: %d files, %.2f GiB" % (nfiles, total / 2 ** 30))
-    buf = torch.empty(total, dtype=torch.uint8, device=dev)
     offs = np.concatenate([[0], np.cumsum(sizes)])
+    host = np.empty(total, dtype=np.uint8)
     for f in range(nfiles):
-        buf[int(offs[f]):int(offs[f + 1])].copy_(torch.from_numpy(synth.mixed(int(sizes[f]), seed=100000 + f)))
+        host[int(offs[f]):int(offs[f + 1])] = synth.mixed(int(sizes[f]), seed=100000 + f)
+    buf = torch.from_numpy(host).to(dev)  # one upload
+    del host
     pb = seq.seqcdc_params_for_avg(16384)
     cut_offs = [0]
     for s in sizes:
@@ -97,6 +135,12 @@ def batched(seq, torch, stream, plan, steps, warmup, dev, tune):
     files = [(buf.data_ptr() + int(offs[f]), int(sizes[f]), 0) for f in range(nfiles)]
     ftab = seq.file_table([f[0] for f in files], sizes)  # marshalled once, like a caller's own table
     otab = seq.offsets_table(cut_offs)
+    return buf, sizes, total, pb, cut_offs, bcuts, bcounts, files, ftab, otab
+
+
+def batched(seq, torch, stream, plan, steps, warmup, dev, tune):
+    nfiles = 4096
+    buf, sizes, total, pb, cut_offs, bcuts, bcounts, files, ftab, otab = batch_workload(seq, torch, dev)
 
     def bstep():
         seq.seqcdc_chunk_batch(ftab, [pb], bcuts.data_ptr(), otab, bcounts.data_ptr(), stream=stream, plan=plan)
@@ -141,9 +185,35 @@ def batched(seq, torch, stream, plan, steps, warmup, dev, tune):
         seq.seqcdc_chunk(files[f][0], files[f][1], pb, bcuts.data_ptr(), pcap, stream=stream, plan=plan)
     torch.cuda.synchronize()
     pdt = time.perf_counter() - t0
+    # the same batch in the direct (skip-aware) resolve mode: no mark kernel, chains read only the windows they scan
+    dplan = seq.seqcdc_plan_create()
+    seq.seqcdc_plan_set_mode(dplan, 1)
+    try:
+        def dstep():
+            seq.seqcdc_chunk_batch(ftab, [pb], bcuts.data_ptr(), otab, bcounts.data_ptr(), stream=stream, plan=dplan)
+        for _ in range(warmup):
+            dstep()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            dstep()
+        torch.cuda.synchronize()
+        ddt = (time.perf_counter() - t0) / steps
+        dsame = bool(np.array_equal(bcounts.cpu().numpy(), counts))
+    finally:
+        seq.seqcdc_plan_destroy(dplan)
+    dtraffic = stored_step_traffic("batched_direct")
+    direct = {"ms_per_step": round(ddt * 1e3, 3), "GBps": round(total / ddt / 1e9, 1), "counts_match": dsame,
+              "traffic": dtraffic,
+              "traffic_per_input_byte": round(dtraffic / total, 4) if dtraffic else None}
+    # whole-step roofline: the two-phase design's algorithmic bytes (marking every byte, writing the cuts) over
+    # the step time; traffic = the counter bytes of every kernel of a step
+    alg = sum(mark_alg_bytes(int(x)) for x in sizes) + 8 * int(counts.sum())
+    roof = step_roofline(alg, bdt * 1e3, stored_step_traffic("batched"))
     del buf, bcuts
     return {"files": nfiles, "bytes": total, "cuts": int(counts.sum()), "ms_per_step": round(bdt * 1e3, 3),
             "GBps": round(total / bdt / 1e9, 1), "frac_hbm_peak_input": round(total / bdt / 1e9 / HBM_PEAK_GBS, 4),
+            "roofline": roof, "direct": direct,
             "graph_ms_per_step": round(gdt * 1e3, 3), "graph_GBps": round(total / gdt / 1e9, 1),
             "graph_counts_match": graph_same,
             "per_file_launch_GBps": round(total / pdt / 1e9, 2), "speedup_vs_per_file": round(pdt / bdt, 2),
@@ -151,8 +221,10 @@ def batched(seq, torch, stream, plan, steps, warmup, dev, tune):
             "tuning": tuning, "counts": counts}
 
 
-def serving(seq, torch, dev, streams=4, max_batch=64):
-    """Poisson request stream through the serving loop; returns latency percentiles per offered load."""
+def serving(seq, torch, dev, streams=2, max_batch=512):
+    """Poisson request stream through the serving loop; returns latency percentiles per offered load.  A run's rate is
+    its bytes over the time from its first submission to its last result (each request's completion = its submission
+    time on the host + the latency the library measured), so the Python loop that collects results is not timed."""
     import synth
     vers = synth.snapshot_series(256 << 20, 3, seed=11, nedits=200, maxlen=4096)
     dvers = [torch.from_numpy(v).to(dev) for v in vers]
@@ -161,17 +233,32 @@ def serving(seq, torch, dev, streams=4, max_batch=64):
     nreq = 400
     sizes = synth.lognormal_sizes(nreq, 1 << 20, 1.5, 1024, 256 << 20, seed=12).astype(np.int64)
     reqs = []
+    meta = []  # (version, offset, length, params index) of each request
     for i in range(nreq):
         v = int(rng.integers(len(vers)))
         n = int(min(sizes[i], vers[v].size))
         off = int(rng.integers(vers[v].size - n + 1))
         reqs.append((dvers[v].data_ptr() + off, n, i % 2))
+        meta.append((v, off, n, i % 2))
     total = sum(r[1] for r in reqs)
     arr = (seq.seqcdc_params * 2)(*params)
-    cfg = seq.seqcdc_server_config(0, 4 << 30, 256, streams, max_batch, 2, arr)
+    cfg = seq.seqcdc_server_config(0, 4 << 30, 1024, streams, max_batch, 2, arr)
     h = ctypes.c_void_p()
     if seq.lib.seqcdc_server_create(ctypes.byref(cfg), ctypes.byref(h)):
         raise RuntimeError(seq.last_error())
+
+    def timeline(npasses):
+        """Summary of the last npasses pass records: host layout, device time, waits, workspace growth."""
+        recs = seq.seqcdc_server_timeline(h)[-npasses:] if npasses else []
+        if not recs:
+            return None
+        g = np.array([r["gpu_ms"] for r in recs])
+        return {"passes": len(recs), "requests_per_pass": round(float(np.mean([r["requests"] for r in recs])), 1),
+                "gpu_ms_sum": round(float(g.sum()), 3), "gpu_ms_max": round(float(g.max()), 3),
+                "layout_ms_mean": round(float(np.mean([r["layout_ms"] for r in recs])), 3),
+                "wait_ms_mean": round(float(np.mean([r["wait_ms"] for r in recs])), 3),
+                "retire_ms_mean": round(float(np.mean([r["retire_ms"] for r in recs])), 3),
+                "grew": int(sum(r["grew"] for r in recs))}
 
     def passes():
         v = ctypes.c_uint64()
@@ -179,36 +266,37 @@ def serving(seq, torch, dev, streams=4, max_batch=64):
             raise RuntimeError(seq.last_error())
         return v.value
 
-    def run(rate_gbs):
-        """Submit reqs at Poisson arrival times for an offered load (GB/s); None = all at once."""
-        tickets = [None] * nreq
+    kept = {}
+
+    ftab = seq.file_table([r[0] for r in reqs], [r[1] for r in reqs], [r[2] for r in reqs])
+
+    def run(rate_gbs, keep=False):
+        """Submit reqs at Poisson arrival times for an offered load (GB/s); None = all at once.  The library queues
+        them (seqcdc_server_submit_many), so the offered rate is not limited by a Python loop.  keep: copy each
+        request's cuts for the parity check made after every measurement."""
         p0 = passes()
+        at_ms = None
         if rate_gbs:
             mean = total / nreq
-            gaps = rng.exponential(mean / (rate_gbs * 1e9), nreq)
-            arrivals = np.cumsum(gaps)
-        else:
-            arrivals = np.zeros(nreq)
-        t0 = time.perf_counter()
-        for i, (ptr, n, pi) in enumerate(reqs):
-            while time.perf_counter() - t0 < arrivals[i]:
-                pass
-            t = ctypes.c_uint64()
-            if seq.lib.seqcdc_server_submit(h, ctypes.c_void_p(ptr), n, pi, ctypes.byref(t)):
-                raise RuntimeError(seq.last_error())
-            tickets[i] = t.value
+            at_ms = np.cumsum(rng.exponential(mean / (rate_gbs * 1e9), nreq)) * 1e3
+        tickets, t_sub = seq.seqcdc_server_submit_many(h, ftab, at_ms)
         lat = []
-        for t in tickets:
+        for i, t in enumerate(tickets):
             res = seq.seqcdc_result()
-            if seq.lib.seqcdc_server_wait(h, t, 60000.0, ctypes.byref(res)):
+            if seq.lib.seqcdc_server_wait(h, int(t), 60000.0, ctypes.byref(res)):
                 raise RuntimeError(seq.last_error())
             lat.append(res.latency_ms)
-            seq.lib.seqcdc_server_release(h, t)
-        dt = time.perf_counter() - t0
+            if keep:
+                kept[i] = np.ctypeslib.as_array(res.cuts, shape=(res.count,)).copy() if res.count else \
+                    np.zeros(0, np.uint64)
+            seq.lib.seqcdc_server_release(h, int(t))
         lat = np.array(lat)
+        dt = float(np.max(t_sub + lat)) * 1e-3  # first submission -> last result (the call starts at 0)
+        np_ = passes() - p0
         return {"offered_GBps": round(rate_gbs, 2) if rate_gbs else None, "GBps": round(total / dt / 1e9, 2),
+                "submit_lag_ms_max": round(float(np.max(t_sub - at_ms)), 3) if at_ms is not None else None,
                 "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                "passes": passes() - p0}
+                "passes": np_, "timeline": timeline(np_)}
 
     try:
         for _ in range(3):  # warm-up: the passes' buffers grow to the largest batches they meet
@@ -216,6 +304,7 @@ def serving(seq, torch, dev, streams=4, max_batch=64):
         sat = run(None)
         peak = sat["GBps"]
         loads = [run(frac * peak) for frac in (0.1, 0.4, 0.8)]
+        run(None, keep=True)  # the results checked against the oracle after every measurement (untimed)
     finally:
         seq.lib.seqcdc_server_destroy(h)
     # plain per-request path: one seqcdc_chunk call per request, back to back
@@ -231,7 +320,11 @@ def serving(seq, torch, dev, streams=4, max_batch=64):
         lat.append((time.perf_counter() - t1) * 1e3)
     dt = time.perf_counter() - t0
     seq.seqcdc_plan_destroy(plan)
-    return {"requests": nreq, "bytes": total, "saturated": sat, "loads": loads,
+    # for the parity check: each request's bytes (version, offset, length) and parameters
+    checks = {"versions": vers, "reqs": meta, "params": params, "got": kept}
+    return {"requests": nreq, "bytes": total, "config": {"streams": streams, "max_batch": max_batch, "ring_slots": 1024,
+                                                          "budget_bytes": 4 << 30},
+            "saturated": sat, "loads": loads, "_checks": checks,
             "plain_per_request": {"GBps": round(total / dt / 1e9, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
                                   "p99_ms": round(float(np.percentile(lat, 99)), 3)}}
 
@@ -303,6 +396,21 @@ def cpu_batched(seq, gpu_counts):
             "counts_match": bool(all(counts[f] == int(gpu_counts[f]) for f in range(nfiles)))}
 
 
+def serving_parity(checks):
+    """Every request of the saturated serving run against the oracle on its own bytes (host side, after the GPU
+    measurements)."""
+    import oracle
+    ok = True
+    for i, (vi, off, n, pi) in enumerate(checks["reqs"]):
+        p = checks["params"][pi]
+        want = oracle.chunk(checks["versions"][vi][off:off + n], mode=p.mode, seq_length=p.seq_length,
+                            min_size=p.min_size, max_size=p.max_size, skip_trigger=p.skip_trigger,
+                            skip_size=p.skip_size)
+        got = checks["got"].get(i)
+        ok = ok and got is not None and got.size == want.size and bool(np.array_equal(got, want))
+    return ok
+
+
 def cpu_baseline(host, p, seconds):
     """The oracle, single-threaded, over whole passes of the same stream until `seconds` of work."""
     import oracle
@@ -341,12 +449,32 @@ def main():
         dst = torch.empty_like(d)
         for _ in range(5):
             dst.copy_(d)  # plain 1 GiB device copy: the calibration kernel
-        groups = (n + 63) // 64
-        eo = torch.empty(4 * groups, dtype=torch.int32, device=dev)
-        for _ in range(5):
-            seq.seqcdc_mark(d.data_ptr(), n, p, eo.data_ptr(), stream=stream)
+        del dst
+        if args.traffic_probe == "mark":
+            groups = (n + 63) // 64
+            eo = torch.empty(4 * groups, dtype=torch.int32, device=dev)
+            for _ in range(5):
+                seq.seqcdc_mark(d.data_ptr(), n, p, eo.data_ptr(), stream=stream)
+        else:
+            plan = seq.seqcdc_plan_create()
+            if args.mode is not None:
+                seq.seqcdc_plan_set_mode(plan, args.mode)
+            if args.traffic_probe == "plain":
+                cap = seq.seqcdc_max_cuts(n, p)
+                cuts = torch.empty(cap, dtype=torch.int64, device=dev)
+                for _ in range(PROBE_STEPS):
+                    seq.seqcdc_chunk(d.data_ptr(), n, p, cuts.data_ptr(), cap, stream=stream, plan=plan)
+            else:
+                del d
+                buf, sizes, total, pb, cut_offs, bcuts, bcounts, files, ftab, otab = batch_workload(seq, torch, dev)
+                for _ in range(PROBE_STEPS):
+                    seq.seqcdc_chunk_batch(ftab, [pb], bcuts.data_ptr(), otab, bcounts.data_ptr(), stream=stream,
+                                           plan=plan)
+                log("probe input bytes: %d" % total)
+            torch.cuda.synchronize()
+            seq.seqcdc_plan_destroy(plan)
         torch.cuda.synchronize()
-        log("traffic probe done")
+        log("traffic probe done: %s, %d steps" % (args.traffic_probe, PROBE_STEPS))
         return
 
     cap = seq.seqcdc_max_cuts(n, p)
@@ -389,6 +517,11 @@ def main():
 
     roofline = mark_roofline(n, float(ph[0]), args.traffic_json)
     roofline["step_share"] = round(roofline["kernel_ms"] / (dt * 1e3), 4)
+    # the whole step against the same peak: the mark kernel's algorithmic bytes plus the cuts, over the step time,
+    # and the counter bytes of every kernel of a step (when taken on these sources)
+    step_alg = mark_alg_bytes(n) + 8 * count
+    roofline["step_frac"] = round(step_alg / dt / 1e9 / HBM_PEAK_GBS, 4)
+    roofline["step"] = step_roofline(step_alg, dt * 1e3, stored_step_traffic("plain"))
     log("mark: %s" % roofline)
 
     extra = {"phases_ms": phases}
@@ -416,7 +549,7 @@ def main():
         log("batched: %s" % extra["batched"])
     if not args.no_serve:
         extra["serving"] = serving(seq, torch, dev)
-        log("serving: %s" % extra["serving"])
+        log("serving: %s" % {k: v for k, v in extra["serving"].items() if k != "_checks"})
     if not args.no_sweep:  # last: its autotuning sets the process-wide choices of more parameter classes
         extra["sweep"] = sweep(seq, torch, stream, d, args.steps, not args.no_tune)
         log("sweep: %s" % extra["sweep"])
@@ -430,6 +563,9 @@ def main():
         if "batched" in extra:
             extra["batched"]["cpu_all_cores"] = cpu_batched(seq, extra["batched"]["counts"])
             log("batched cpu context: %s" % extra["batched"]["cpu_all_cores"])
+        if "serving" in extra:
+            extra["serving"]["parity_vs_oracle"] = serving_parity(extra["serving"]["_checks"])
+            log("serving parity %s" % extra["serving"]["parity_vs_oracle"])
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True, "scaling": "weak",
@@ -440,6 +576,8 @@ def main():
            "roofline": roofline, "cpu_baseline": cpu}
     if "batched" in extra:
         extra["batched"].pop("counts", None)
+    if "serving" in extra:
+        extra["serving"].pop("_checks", None)
     out.update(extra)
     print(json.dumps(out), flush=True)
     seq.seqcdc_plan_destroy(plan)

@@ -81,7 +81,10 @@ int seqcdc_plan_destroy(seqcdc_plan* plan);
 
 /* Tuning knobs of a plan (0 = keep).  segment_bytes: length of the segments
  * a stream is split into for speculative resolution (rounded up to a whole
- * number of mark spans; default 128 x min_size, at least 64 KiB); mark_span_blocks: 1 KiB blocks per mark span, the
+ * number of mark spans; default: the autotuner's choice, else 128 x
+ * min_size; a call on a single stream shortens it down to the stream's bytes
+ * divided by the device's chain waves (CUs x waves_per_cu), but not below
+ * 64 KiB x (min_size / 4 KiB)^2, and at least 64 KiB); mark_span_blocks: 1 KiB blocks per mark span, the
  * unit of marking work (4, 8, 16, 32 or 64); waves_per_cu: waves per compute
  * unit of the persistent chain kernels, one chain per wave (4..32, a
  * multiple of 4; default 8; each wave keeps 8 KiB of windows in LDS, so at
@@ -241,18 +244,22 @@ int seqcdc_dedup_stats(const uint8_t* const* h_buffers, const uint64_t* const* h
 
 /* ---------------------------------------------------------------------
  * Serving: a dedup-ingest request loop with continuous batching.
- * Requests reference device-resident bytes.  A scheduler thread admits
- * queued requests while the bytes in flight plus their workspaces fit the
- * memory budget and a ring slot is free, launches each admitted group as one
- * batched pass on one of `streams` HIP streams (groups overlap on the GPU),
- * and publishes each request's cuts and latency when its pass completes.
+ * Requests reference device-resident bytes.  The memory budget is split
+ * evenly between `streams` passes; at creation each pass reserves, once, the
+ * workspace for the largest group of requests its share can hold (its input
+ * capacity plus that workspace fit the share), so admission and passes never
+ * allocate or free.  A scheduler thread admits queued requests into a free
+ * pass while their bytes fit its capacity and a ring slot is free, launches
+ * each admitted group as one batched pass on the pass's HIP stream (groups
+ * overlap on the GPU), and publishes each request's cuts and latency when its
+ * pass completes.  The oldest queued request is never overtaken.
  * Passes use the phased resolve launches without overlapped groups and 8
  * chain waves per compute unit; segment length and mark span follow the
  * autotuner's choices, if any. 
  * ------------------------------------------------------------------- */
 typedef struct {
   int device;                /* -1 = current */
-  uint64_t budget_bytes;     /* device memory for in-flight requests (inputs counted, workspaces included) */
+  uint64_t budget_bytes;     /* in-flight input bytes plus the passes' workspaces (reserved at creation) */
   uint32_t ring_slots;       /* max requests in flight */
   uint32_t streams;          /* concurrent batched passes (1..8) */
   uint32_t max_batch;        /* max requests per pass */
@@ -271,17 +278,44 @@ typedef struct {
 
 typedef struct seqcdc_server seqcdc_server;
 int seqcdc_server_create(const seqcdc_server_config* cfg, seqcdc_server** out);
-/* Queue a request; *ticket identifies it.  SEQCDC_EBUDGET if it could never fit the budget. */
+/* Queue a request; *ticket identifies it.  SEQCDC_EBUDGET if it is larger
+ * than one pass can hold (budget / streams less that pass's workspace). */
 int seqcdc_server_submit(seqcdc_server* s, const void* d_data, uint64_t n, uint32_t params_index, uint64_t* ticket);
+/* Queue n requests (d_data, n and params_index of each seqcdc_file; reserved
+ * must be 0) from one call, each with its own ticket, as n separate submits
+ * would.  at_ms == NULL: all at once.  Otherwise request i is queued at_ms[i]
+ * milliseconds after the call starts (non-decreasing offsets; the call
+ * returns after the last one), which replays an arrival process at rates a
+ * caller's own loop could not reach.  submitted_ms (may be NULL) receives
+ * when each request was queued, in milliseconds after the call started.
+ * Every request is validated first: on an error nothing is queued. */
+int seqcdc_server_submit_many(seqcdc_server* s, const seqcdc_file* reqs, uint32_t n, const double* at_ms,
+                              uint64_t* tickets, double* submitted_ms);
 /* Non-blocking: fills *out; returns 0 when done, SEQCDC_EAGAIN while pending. */
 int seqcdc_server_poll(seqcdc_server* s, uint64_t ticket, seqcdc_result* out);
 /* Block until the ticket is done (timeout_ms < 0: no limit). */
 int seqcdc_server_wait(seqcdc_server* s, uint64_t ticket, double timeout_ms, seqcdc_result* out);
 /* Free the host copy of a finished request's cuts. */
 int seqcdc_server_release(seqcdc_server* s, uint64_t ticket);
-/* Counters: requests admitted, passes launched, peak bytes in flight, peak requests in flight. */
+/* Counters: requests admitted, passes launched, peak bytes (input bytes in
+ * flight plus the passes' reserved workspaces; never above the budget), peak
+ * requests in flight. */
 int seqcdc_server_stats(seqcdc_server* s, uint64_t* admitted, uint64_t* passes, uint64_t* peak_bytes,
                         uint64_t* peak_inflight);
+
+/* One batched pass of the serving loop, for diagnosing throughput. */
+typedef struct {
+  uint32_t requests;  /* requests in the pass */
+  uint32_t grew;      /* workspace buffers (re)allocated while the pass was laid out (each frees the old one) */
+  uint64_t bytes;     /* input bytes */
+  double wait_ms;     /* admission -> the scheduler starts laying the pass out */
+  double layout_ms;   /* host: tables laid out and every launch and copy of the pass enqueued */
+  double gpu_ms;      /* device: the pass's work on its stream, kernels and result copies (HIP events) */
+  double retire_ms;   /* enqueue done -> the scheduler saw the pass complete and published its results */
+} seqcdc_pass_record;
+/* The most recent passes (up to 4096 are kept), oldest first: writes up to
+ * cap records to out and their number to *count. */
+int seqcdc_server_timeline(seqcdc_server* s, seqcdc_pass_record* out, uint32_t cap, uint32_t* count);
 int seqcdc_server_destroy(seqcdc_server* s);
 
 /* Description of the calling thread's most recent failure ("" if none). */

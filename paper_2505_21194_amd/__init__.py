@@ -50,6 +50,11 @@ class seqcdc_result(ctypes.Structure):
                 ("latency_ms", ctypes.c_double), ("queue_ms", ctypes.c_double)]
 
 
+class seqcdc_pass_record(ctypes.Structure):
+    _fields_ = [("requests", _u32), ("grew", _u32), ("bytes", _u64), ("wait_ms", ctypes.c_double),
+                ("layout_ms", ctypes.c_double), ("gpu_ms", ctypes.c_double), ("retire_ms", ctypes.c_double)]
+
+
 class SeqCDCError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("seqcdc error %d: %s" % (code, msg))
@@ -95,11 +100,14 @@ _SIGS = {
                             ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "seqcdc_server_create": ([ctypes.POINTER(seqcdc_server_config), ctypes.POINTER(_p)], ctypes.c_int),
     "seqcdc_server_submit": ([_p, _p, _u64, _u32, ctypes.POINTER(_u64)], ctypes.c_int),
+    "seqcdc_server_submit_many": ([_p, ctypes.POINTER(seqcdc_file), _u32, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "seqcdc_server_poll": ([_p, _u64, ctypes.POINTER(seqcdc_result)], ctypes.c_int),
     "seqcdc_server_wait": ([_p, _u64, ctypes.c_double, ctypes.POINTER(seqcdc_result)], ctypes.c_int),
     "seqcdc_server_release": ([_p, _u64], ctypes.c_int),
     "seqcdc_server_stats": ([_p, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64),
                              ctypes.POINTER(_u64)], ctypes.c_int),
+    "seqcdc_server_timeline": ([_p, ctypes.POINTER(seqcdc_pass_record), _u32, ctypes.POINTER(_u32)], ctypes.c_int),
     "seqcdc_server_destroy": ([_p], ctypes.c_int),
     "seqcdc_last_error": ([], ctypes.c_char_p),
 }
@@ -301,6 +309,34 @@ def seqcdc_batch_destroy(batch):
 
 def seqcdc_mark(d_stream, n, params, d_eo, stream=None):
     _check(lib.seqcdc_mark(d_stream, n, ctypes.byref(_as_params(params)), d_eo, _stream_handle(stream)))
+
+
+def seqcdc_server_submit_many(server, files, at_ms=None):
+    """Queue requests (a file_table() or a list of (device_ptr, n, params_index)), optionally at arrival offsets in
+    ms from the call; returns (tickets, submitted_ms) as numpy arrays."""
+    import numpy as np
+    if isinstance(files, ctypes.Array):
+        farr, nf = files, getattr(files, "_len", len(files))
+    else:
+        farr = file_table([f[0] for f in files], [f[1] for f in files], [f[2] for f in files])
+        nf = len(files)
+    tickets = np.zeros(max(nf, 1), dtype=np.uint64)
+    sub = np.zeros(max(nf, 1), dtype=np.float64)
+    at = None
+    if at_ms is not None:
+        at_arr = np.ascontiguousarray(at_ms, dtype=np.float64)
+        at = at_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib.seqcdc_server_submit_many(server, farr, nf, at, tickets.ctypes.data_as(ctypes.POINTER(_u64)),
+                                         sub.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return tickets[:nf], sub[:nf]
+
+
+def seqcdc_server_timeline(server, cap=4096):
+    """The server's most recent pass records (oldest first) as a list of dicts."""
+    recs = (seqcdc_pass_record * cap)()
+    n = _u32()
+    _check(lib.seqcdc_server_timeline(server, recs, cap, ctypes.byref(n)))
+    return [{k: getattr(recs[i], k) for k, _ in seqcdc_pass_record._fields_} for i in range(n.value)]
 
 
 def seqcdc_dedup_stats(buffers, cut_lists):

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -58,8 +59,13 @@ u64 max_cuts(u64 n, const seqcdc_params* p) { return n ? n / p->min_size + 1 : 0
 static u64 round_up(u64 v, u64 a) { return (v + a - 1) / a * a; }
 
 // ---------------------------------------------------------------- buffers
+static std::atomic<u64> g_reallocs{0};
+
+u64 realloc_count() { return g_reallocs.load(std::memory_order_relaxed); }
+
 int DevBuf::reserve(size_t bytes) {
   if (bytes <= cap) return SEQCDC_OK;
+  g_reallocs.fetch_add(1, std::memory_order_relaxed);
   if (p) {
     (void)hipFree(p);
     p = nullptr;
@@ -84,6 +90,7 @@ void DevBuf::release() {
 
 int HostBuf::reserve(size_t bytes) {
   if (bytes <= cap) return SEQCDC_OK;
+  g_reallocs.fetch_add(1, std::memory_order_relaxed);
   if (p) (void)hipHostFree(p);
   p = nullptr;
   cap = 0;
@@ -147,13 +154,26 @@ TuneKey plan_key(const Plan* pl, const seqcdc_params* p) {
   return k;
 }
 
-// Segment length for speculative resolution of a stream of n bytes.
-u64 Plan::segment_for(u64 n, const seqcdc_params* p) const {
+// Segment length for speculative resolution of a stream of n bytes.  Unless
+// set explicitly, the tuned (else default) length; a call on one stream
+// (single = true) uses no longer segments than needed for its chains to fill
+// every chain wave of the device once, so a small stream is cut into more,
+// shorter chains, which finish sooner.  Not below 64 KiB x (min_size /
+// 4 KiB)^2: the distance two chains take to resynchronise grows about with
+// the square of the chunk size, and segments much shorter than it only add
+// boundaries whose continuations set the time.  Calls on many files keep the
+// tuned length: the files supply the parallelism, and more boundaries only
+// lengthen the continuations.
+u64 Plan::segment_for(u64 n, const seqcdc_params* p, bool single) const {
   u64 seg = seg_override;
   if (!seg) {
     TuneEntry te;
     if (tune_lookup(plan_key(this, p), &te)) seg = te.seg_mult * p->min_size;
     else seg = 128 * p->min_size;
+    const u64 fill = n / ((u64)cus * waves_for(p));
+    const u64 m = p->min_size >> 12;  // min_size in 4 KiB
+    const u64 floor = m > 1 ? (64 * 1024) * std::min<u64>(m * m, 1u << 20) : 64 * 1024;
+    if (single && fill < seg) seg = std::max<u64>(fill, std::min<u64>(floor, seg));
   }
   seg = std::max<u64>(seg, 64 * 1024);
   if (n / seg > kMaxSegments) seg = n / kMaxSegments + 1;
@@ -258,6 +278,57 @@ static int ensure_side(Plan* pl) {
   return SEQCDC_OK;
 }
 
+// Continuation buffer entries per chain for segments of seg bytes.
+static u32 cont_cap_for(u64 seg, u64 min_size) {
+  return (u32)std::max<u64>(1024, std::min<u64>(2 * seg / min_size + 64, 4096));
+}
+
+// Reserves the plan's workspaces for any call on at most `bytes` input bytes
+// in at most `nfiles` files under these parameter sets, with the plan's
+// current tuning (bounds of what run_batch reserves), so such calls allocate
+// nothing.  Tuning changed later (a smaller segment length) may make a call
+// grow them once.  *total (may be NULL) receives the bytes the workspaces
+// take (device plus pinned host); dry: compute it only.
+int plan_reserve(Plan* pl, u64 bytes, u32 nfiles, const seqcdc_params* params, u32 nparams, bool dry, u64* total) {
+  if (total) *total = 0;
+  if (!nparams || !nfiles) return SEQCDC_OK;
+  u64 min_min = ~0ull, seg_min = ~0ull;
+  u32 cont_cap = 64, span_min = 64;
+  for (u32 i = 0; i < nparams; i++) {
+    const seqcdc_params* p = &params[i];
+    const u64 seg = pl->segment_for(bytes, p, false);  // the longest
+    min_min = std::min<u64>(min_min, p->min_size);
+    seg_min = std::min<u64>(seg_min, seg);
+    cont_cap = std::max<u32>(cont_cap, cont_cap_for(seg, p->min_size));
+    span_min = std::min<u32>(span_min, pl->span_blocks_for(p));
+  }
+  // shorter segments fill the device once at most (cus x waves chains), and
+  // are never shorter than 64 KiB
+  u32 waves = 0;
+  for (u32 i = 0; i < nparams; i++) waves = std::max<u32>(waves, pl->waves_for(&params[i]));
+  const u64 nchains =
+      nfiles + std::min<u64>(std::max<u64>(bytes / seg_min, (u64)pl->cus * waves), bytes / (64 * 1024)) + 1;
+  const u64 spans = bytes / ((u64)span_min * kMarkBlock) + nfiles;
+  const u64 nhint = spans / kHintSpans + 2;
+  const size_t chain_bytes = carve_size({nchains * 4, nchains * 8, nchains * 4, nchains * 4, nchains * 4, nchains * 4,
+                                         nchains * 4, nchains * 4, nchains * 8, nchains * 4, nchains * 8});
+  const size_t table_bytes = carve_size({nfiles * sizeof(FileDesc), nchains * 4, nchains * 8, nchains * 8,
+                                         nchains * 4, nchains * 4 + 4, nfiles * 4ull + 4, nchains * 4 + 4, nhint * 4});
+  const size_t sizes[8] = {bytes / 4 + 16ull * nfiles + 512, bytes / 1024 + 32ull * nfiles + 256,
+                           (bytes / min_min + 2 * nchains) * 8, nchains * cont_cap * 8, chain_bytes, table_bytes,
+                           16 * (kMaxGroups + 2) * 4, table_bytes};
+  DevBuf* bufs[7] = {&pl->eo, &pl->esum, &pl->list, &pl->cont, &pl->chains, &pl->tables, &pl->flags};
+  u64 sum = 0;
+  for (size_t i = 0; i < 8; i++) sum += std::max<size_t>(sizes[i] + sizes[i] / 4, 4096);  // as reserve() rounds
+  if (total) *total = sum;
+  if (dry) return SEQCDC_OK;
+  int rc;
+  for (int i = 0; i < 7; i++)
+    if ((rc = bufs[i]->reserve(sizes[i]))) return rc;
+  if ((rc = pl->staging.reserve(sizes[7]))) return rc;
+  return SEQCDC_OK;
+}
+
 // Prepare and enqueue the whole pipeline for `specs` on `st`.
 // mark_only: run the mark step only (eo destination = specs[0].out as u32*).
 int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark_only) {
@@ -303,7 +374,7 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
     eo_bytes += 16 * ((s.n + 63) / 64);
     d.esum = (uint8_t*)(uintptr_t)esum_bytes;
     esum_bytes += round_up((s.n + 1023) / 1024, 16) + 16;
-    d.seg = pl->segment_for(s.n, s.p);
+    d.seg = pl->segment_for(s.n, s.p, nfiles == 1);
     d.nseg = s.n > d.seg ? (u32)((s.n + d.seg - 1) / d.seg) : 1;
     d.chain0 = nchains;
     nchains += d.nseg;
@@ -312,7 +383,7 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
     d.out_count = s.out_count;
     if (d.nseg > 1) {
       multi.push_back(f);
-      cont_cap = std::max<u32>(cont_cap, (u32)std::max<u64>(1024, std::min<u64>(2 * d.seg / d.min_size + 64, 4096)));
+      cont_cap = std::max<u32>(cont_cap, cont_cap_for(d.seg, d.min_size));
     }
   }
   if (mark_only) {
@@ -748,7 +819,7 @@ int seqcdc_plan_get_tuning(seqcdc_plan* plan, uint64_t n, const seqcdc_params* p
   int rc = validate(p);
   if (rc) return rc;
   Plan* pl = (Plan*)plan;
-  if (segment_bytes) *segment_bytes = pl->segment_for(n, p);
+  if (segment_bytes) *segment_bytes = pl->segment_for(n, p, true);
   if (mark_span_blocks) *mark_span_blocks = pl->span_blocks_for(p);
   if (waves_per_cu) *waves_per_cu = pl->waves_for(p);
   return SEQCDC_OK;

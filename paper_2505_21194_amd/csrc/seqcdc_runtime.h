@@ -16,6 +16,10 @@ constexpr u64 kMaxSegments = 65536;  // per stream
 constexpr u32 kMaxGroups = 8;        // file groups of an overlapped batch
 constexpr u64 kMaxStream = 1ull << 38;  // 256 GiB: group and sub-window indices stay 32-bit
 
+// Workspace (re)allocations made by DevBuf / HostBuf since the process
+// started (each frees the old buffer: hipFree / hipHostFree synchronise).
+u64 realloc_count();
+
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
@@ -79,7 +83,7 @@ struct Plan {
   hipEvent_t ev_mark[kMaxGroups] = {};
   hipEvent_t ev_chain_first = nullptr, ev_chain_last = nullptr, ev_join = nullptr;
 
-  u64 segment_for(u64 n, const seqcdc_params* p) const;
+  u64 segment_for(u64 n, const seqcdc_params* p, bool single) const;
   u32 span_blocks_for(const seqcdc_params* p) const;
   u32 waves_for(const seqcdc_params* p) const;
   int mode_for(const seqcdc_params* p) const;
@@ -112,6 +116,7 @@ int chunk_batch(Plan* pl, const seqcdc_file* files, u32 nfiles, const seqcdc_par
 int build_specs(const seqcdc_file* files, u32 nfiles, const seqcdc_params* params, u32 nparams, u64* d_cuts,
                 const u64* h_off, u64* d_counts, std::vector<Spec>& specs);
 int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark_only);
+int plan_reserve(Plan* pl, u64 bytes, u32 nfiles, const seqcdc_params* params, u32 nparams, bool dry, u64* total);
 TuneKey plan_key(const Plan* pl, const seqcdc_params* p);
 bool tune_lookup(const TuneKey& k, TuneEntry* out);
 void tune_store(const TuneEntry& e);

@@ -1,14 +1,19 @@
 // Serving: a dedup-ingest request loop with continuous batching.
 //
-// Requests reference device-resident bytes.  A scheduler thread admits queued
-// requests while the device memory they need (input bytes, mark bitmaps,
-// segment lists and cut output) fits the budget and a ring slot is free,
-// groups them (up to max_batch) into one batched pass on a free stream, and
-// keeps admitting while earlier passes run: passes on different streams
-// overlap on the GPU.  When a pass's event completes, each request's cuts are
-// published to host memory with its latency.  A request that has waited longer
-// than all others and does not fit blocks further admission until it does, so
-// large requests are not starved by a stream of small ones.
+// Requests reference device-resident bytes.  The budget is split evenly
+// between the passes (one per stream).  At creation each pass reserves, once,
+// the workspace (mark bitmaps, segment lists, continuation buffers, tables,
+// cut output on the device and in pinned host memory) for the largest group
+// of requests its share can hold: its input capacity plus that workspace fit
+// the share.  A scheduler thread admits queued requests into a free pass while
+// their bytes fit its capacity and a ring slot is free (up to max_batch per
+// pass) and launches the group as one batched pass on the pass's stream; it
+// keeps admitting while earlier passes run, so passes on different streams
+// overlap on the GPU, and nothing is allocated or freed on this path.  When a
+// pass's event completes, each request's cuts are published to host memory
+// with its latency.  The oldest queued request is never overtaken: it waits
+// for a free pass, which can always hold it, so large requests are not starved
+// by a stream of small ones.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,10 +50,14 @@ struct Request {
   std::vector<u64> cuts;
 };
 
+constexpr size_t kTimelineKeep = 4096;  // pass records kept for seqcdc_server_timeline
+
 struct Pass {
   bool busy = false;
   hipStream_t stream = nullptr;
-  hipEvent_t done = nullptr;
+  hipEvent_t start = nullptr, done = nullptr;  // timing events around the pass's work on its stream
+  seqcdc_pass_record rec{};                    // the pass in flight
+  Clock::time_point t_admit, t_enqueued;
   Plan plan;
   DevBuf d_cuts, d_counts;
   HostBuf h_cuts, h_counts;
@@ -60,7 +69,6 @@ struct Pass {
 struct Server {
   seqcdc_server_config cfg;
   std::vector<seqcdc_params> params;
-  u64 min_min = 0;
   std::vector<Pass*> passes;
   std::mutex mu;
   std::condition_variable cv_sched, cv_done;
@@ -69,17 +77,24 @@ struct Server {
   u64 next_ticket = 1;
   u64 bytes_inflight = 0, reqs_inflight = 0;
   u64 stat_admitted = 0, stat_passes = 0, stat_peak_bytes = 0, stat_peak_reqs = 0;
+  std::deque<seqcdc_pass_record> timeline;  // the latest passes, oldest first
   bool stop = false;
   std::thread th;
   int thread_err = SEQCDC_OK;
 
+  u64 pass_cap = 0;   // input bytes one pass can hold (its workspace is reserved for them)
+  u64 workspace = 0;  // device and pinned bytes all passes reserved at creation
+  u64 min_min = ~0ull;
+
   u64 cost_of(u64 n, const seqcdc_params& p) const {
-    // input + EO16 bitmaps + per-segment lists + cut output (device) + fixed overhead
-    return n + 16 * ((n + 63) / 64) + 16 * (n / p.min_size + 2) + (64 << 10);
+    (void)p;
+    return n;  // input bytes; the workspace is reserved per pass
   }
 };
 
 static int launch_pass(Server* s, Pass* ps) {
+  const auto t0 = Clock::now();
+  const u64 reallocs0 = realloc_count();
   const u32 nf = (u32)ps->reqs.size();
   std::vector<seqcdc_file> files(nf);
   ps->offs.assign(nf + 1, 0);
@@ -90,6 +105,8 @@ static int launch_pass(Server* s, Pass* ps) {
   }
   const u64 total = ps->offs[nf];
   int rc;
+  hipError_t e0 = hipEventRecord(ps->start, ps->stream);
+  if (e0 != hipSuccess) return hip_fail(e0, "serving pass");
   if ((rc = ps->d_cuts.reserve(total * 8))) return rc;
   if ((rc = ps->d_counts.reserve(nf * 8))) return rc;
   if ((rc = ps->h_cuts.reserve(total * 8))) return rc;
@@ -102,14 +119,29 @@ static int launch_pass(Server* s, Pass* ps) {
   if (e == hipSuccess) e = hipEventRecord(ps->done, ps->stream);
   if (e != hipSuccess) return hip_fail(e, "serving pass");
   ps->busy = true;
+  ps->t_enqueued = Clock::now();
+  ps->rec.requests = nf;
+  ps->rec.bytes = 0;
+  for (Request* r : ps->reqs) ps->rec.bytes += r->n;
+  ps->rec.grew = (u32)(realloc_count() - reallocs0);
+  ps->rec.wait_ms = ms_between(ps->t_admit, t0);
+  ps->rec.layout_ms = ms_between(t0, ps->t_enqueued);
   return SEQCDC_OK;
 }
 
 static void finish_pass(Server* s, Pass* ps, int status) {
   const u64* counts = (const u64*)ps->h_counts.p;
   const u64* cuts = (const u64*)ps->h_cuts.p;
+  float gpu_ms = 0;
+  if (status == SEQCDC_OK && hipEventElapsedTime(&gpu_ms, ps->start, ps->done) != hipSuccess) gpu_ms = -1;
   std::lock_guard<std::mutex> g(s->mu);
   const auto now = Clock::now();
+  if (status == SEQCDC_OK) {
+    ps->rec.gpu_ms = gpu_ms;
+    ps->rec.retire_ms = ms_between(ps->t_enqueued, now);
+    s->timeline.push_back(ps->rec);
+    if (s->timeline.size() > kTimelineKeep) s->timeline.pop_front();
+  }
   for (size_t i = 0; i < ps->reqs.size(); i++) {
     Request* r = ps->reqs[i];
     if (status == SEQCDC_OK) {
@@ -156,7 +188,7 @@ static void scheduler(Server* s) {
       if (free_pass) {
         for (auto it = s->queue.begin(); it != s->queue.end() && group.size() < s->cfg.max_batch;) {
           Request* r = *it;
-          const bool fits = s->bytes_inflight + group_bytes + r->cost <= s->cfg.budget_bytes &&
+          const bool fits = group_bytes + r->cost <= s->pass_cap &&
                             s->reqs_inflight + group.size() < s->cfg.ring_slots;
           if (fits) {
             group.push_back(r);
@@ -177,11 +209,12 @@ static void scheduler(Server* s) {
       }
       const auto now = Clock::now();
       for (Request* r : group) r->t_admit = now;
+      free_pass->t_admit = now;
       s->bytes_inflight += group_bytes;
       s->reqs_inflight += group.size();
       s->stat_admitted += group.size();
       s->stat_passes++;
-      s->stat_peak_bytes = std::max(s->stat_peak_bytes, s->bytes_inflight);
+      s->stat_peak_bytes = std::max(s->stat_peak_bytes, s->bytes_inflight + s->workspace);
       s->stat_peak_reqs = std::max(s->stat_peak_reqs, s->reqs_inflight);
     }
     free_pass->reqs = group;
@@ -229,8 +262,13 @@ int seqcdc_server_create(const seqcdc_server_config* cfg, seqcdc_server** out) {
     ps->plan.waves_override = kServerWaves;
     hipError_t e = hipSuccess;
     if (!rc) e = hipStreamCreateWithFlags(&ps->stream, hipStreamNonBlocking);
-    if (!rc && e == hipSuccess) e = hipEventCreateWithFlags(&ps->done, hipEventDisableTiming);
+    if (!rc && e == hipSuccess) e = hipEventCreate(&ps->start);
+    if (!rc && e == hipSuccess) e = hipEventCreate(&ps->done);
     if (rc || e != hipSuccess) {
+      if (ps->done) (void)hipEventDestroy(ps->done);
+      if (ps->start) (void)hipEventDestroy(ps->start);
+      if (ps->stream) (void)hipStreamDestroy(ps->stream);
+      if (!rc) plan_free(&ps->plan);
       delete ps;
       for (Pass* p : s->passes) {
         plan_free(&p->plan);
@@ -241,8 +279,114 @@ int seqcdc_server_create(const seqcdc_server_config* cfg, seqcdc_server** out) {
     }
     s->passes.push_back(ps);
   }
+  // Each pass's share of the budget holds its input capacity plus the
+  // workspace reserved for it; shrink the capacity until both fit.
+  for (u32 i = 0; i < cfg->nparams; i++) s->min_min = std::min<u64>(s->min_min, cfg->params[i].min_size);
+  const u64 share = cfg->budget_bytes / cfg->streams;
+  const u32 nb = cfg->max_batch;
+  auto need = [&](u64 cap) {
+    u64 ws = 0;
+    (void)plan_reserve(&s->passes[0]->plan, cap, nb, s->params.data(), cfg->nparams, true, &ws);
+    const u64 cuts = (cap / s->min_min + nb) * 8;
+    return cap + ws + 2 * (cuts + cuts / 4) + 4 * (nb * 8 + 4096);
+  };
+  u64 cap = share;
+  for (int it = 0; it < 64 && cap > 0 && need(cap) > share; it++)
+    cap = (u64)((double)cap * (double)share / (double)need(cap) * 0.985);
+  int rc = (cap == 0 || need(cap) > share) ? fail(SEQCDC_EINVAL, "budget too small for %u streams", cfg->streams)
+                                           : SEQCDC_OK;
+  s->pass_cap = cap;
+  const u64 cuts = (cap / s->min_min + nb) * 8;
+  for (Pass* ps : s->passes) {
+    if (rc) break;
+    u64 ws = 0;
+    rc = plan_reserve(&ps->plan, cap, nb, s->params.data(), cfg->nparams, false, &ws);
+    if (!rc) rc = ps->d_cuts.reserve(cuts);
+    if (!rc) rc = ps->h_cuts.reserve(cuts);
+    if (!rc) rc = ps->d_counts.reserve(nb * 8);
+    if (!rc) rc = ps->h_counts.reserve(nb * 8);
+    s->workspace += ws + ps->d_cuts.cap + ps->h_cuts.cap + ps->d_counts.cap + ps->h_counts.cap;
+  }
+  if (rc) {
+    for (Pass* p : s->passes) {
+      plan_free(&p->plan);
+      p->d_cuts.release();
+      p->h_cuts.release();
+      p->d_counts.release();
+      p->h_counts.release();
+      if (p->done) (void)hipEventDestroy(p->done);
+      if (p->start) (void)hipEventDestroy(p->start);
+      if (p->stream) (void)hipStreamDestroy(p->stream);
+      delete p;
+    }
+    delete s;
+    return rc;
+  }
   s->th = std::thread(scheduler, s);
   *out = (seqcdc_server*)s;
+  return SEQCDC_OK;
+}
+
+int seqcdc_server_submit_many(seqcdc_server* sv, const seqcdc_file* reqs, uint32_t n, const double* at_ms,
+                              uint64_t* tickets, double* submitted_ms) {
+  Server* s = (Server*)sv;
+  if (!s || (n && (!reqs || !tickets))) return fail(SEQCDC_EINVAL, "NULL argument");
+  for (uint32_t i = 0; i < n; i++) {
+    const seqcdc_file& f = reqs[i];
+    if (f.reserved) return fail(SEQCDC_EINVAL, "request %u: reserved must be 0", i);
+    if (f.params_index >= s->params.size()) return fail(SEQCDC_EINVAL, "request %u: params_index out of range", i);
+    if (f.n && !f.d_data) return fail(SEQCDC_EINVAL, "request %u: NULL data", i);
+    if (s->cost_of(f.n, s->params[f.params_index]) > s->pass_cap)
+      return fail(SEQCDC_EBUDGET, "request %u is larger than a pass can hold (%llu bytes)", i,
+                  (unsigned long long)s->pass_cap);
+    if (at_ms && i && at_ms[i] < at_ms[i - 1]) return fail(SEQCDC_EINVAL, "at_ms must not decrease");
+  }
+  std::vector<Request*> rs(n);
+  for (uint32_t i = 0; i < n; i++) {
+    rs[i] = new (std::nothrow) Request();
+    if (!rs[i]) {
+      for (uint32_t j = 0; j < i; j++) delete rs[j];
+      return fail(SEQCDC_ENOMEM, "request allocation failed");
+    }
+    rs[i]->data = reqs[i].d_data;
+    rs[i]->n = reqs[i].n;
+    rs[i]->pidx = reqs[i].params_index;
+    rs[i]->cost = s->cost_of(reqs[i].n, s->params[reqs[i].params_index]);
+  }
+  const auto t0 = Clock::now();
+  uint32_t i = 0;
+  while (i < n) {
+    // queue every request that is due, under one lock
+    const double now_ms = ms_between(t0, Clock::now());
+    uint32_t j = i;
+    if (!at_ms) j = n;
+    else
+      while (j < n && at_ms[j] <= now_ms) j++;
+    if (j == i) {  // the next arrival is in the future: wait for it (short sleeps, then spin)
+      const double ahead = at_ms[i] - now_ms;
+      if (ahead > 0.2) std::this_thread::sleep_for(std::chrono::microseconds((long)((ahead - 0.1) * 1000)));
+      continue;
+    }
+    std::lock_guard<std::mutex> g(s->mu);
+    const auto t_sub = Clock::now();
+    for (uint32_t k = i; k < j; k++) {
+      Request* r = rs[k];
+      r->t_submit = t_sub;
+      r->ticket = s->next_ticket++;
+      tickets[k] = r->ticket;
+      if (submitted_ms) submitted_ms[k] = ms_between(t0, t_sub);
+      s->all[r->ticket] = r;
+      if (r->n == 0) {
+        r->status = SEQCDC_OK;
+        r->t_admit = r->t_done = t_sub;
+      } else {
+        s->queue.push_back(r);
+      }
+    }
+    s->cv_sched.notify_one();
+    s->cv_done.notify_all();
+    i = j;
+  }
   return SEQCDC_OK;
 }
 
@@ -258,10 +402,10 @@ int seqcdc_server_submit(seqcdc_server* sv, const void* d_data, uint64_t n, uint
   r->pidx = pidx;
   r->cost = s->cost_of(n, s->params[pidx]);
   r->t_submit = Clock::now();
-  if (r->cost > s->cfg.budget_bytes) {
+  if (r->cost > s->pass_cap) {
     delete r;
-    return fail(SEQCDC_EBUDGET, "request needs %llu bytes, budget is %llu", (unsigned long long)s->cost_of(n, s->params[pidx]),
-                (unsigned long long)s->cfg.budget_bytes);
+    return fail(SEQCDC_EBUDGET, "request of %llu bytes is larger than a pass can hold (%llu bytes of the %llu budget)",
+                (unsigned long long)n, (unsigned long long)s->pass_cap, (unsigned long long)s->cfg.budget_bytes);
   }
   std::lock_guard<std::mutex> g(s->mu);
   r->ticket = s->next_ticket++;
@@ -335,6 +479,17 @@ int seqcdc_server_stats(seqcdc_server* sv, uint64_t* admitted, uint64_t* passes,
   return SEQCDC_OK;
 }
 
+int seqcdc_server_timeline(seqcdc_server* sv, seqcdc_pass_record* out, uint32_t cap, uint32_t* count) {
+  Server* s = (Server*)sv;
+  if (!s || !count || (!out && cap)) return fail(SEQCDC_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  const size_t n = std::min<size_t>(cap, s->timeline.size());
+  const size_t first = s->timeline.size() - n;
+  for (size_t i = 0; i < n; i++) out[i] = s->timeline[first + i];
+  *count = (uint32_t)n;
+  return SEQCDC_OK;
+}
+
 int seqcdc_server_destroy(seqcdc_server* sv) {
   Server* s = (Server*)sv;
   if (!s) return SEQCDC_OK;
@@ -352,6 +507,7 @@ int seqcdc_server_destroy(seqcdc_server* sv) {
     ps->h_cuts.release();
     ps->h_counts.release();
     if (ps->done) (void)hipEventDestroy(ps->done);
+    if (ps->start) (void)hipEventDestroy(ps->start);
     if (ps->stream) (void)hipStreamDestroy(ps->stream);
     delete ps;
   }

@@ -9,7 +9,10 @@ and JSON summaries kept with the project:
 * ``traffic FETCH_DB WRITE_DB``: HBM bytes per dispatch of one kernel from
   two ``--pmc`` runs (``FETCH_SIZE`` and ``WRITE_SIZE``, reported in KiB per
   dispatch), scaled by what the same counters read for a plain copy kernel of
-  known size in the same run.
+  known size in the same run;
+* ``step FETCH_DB WRITE_DB``: the same for a whole chunking step, summed over
+  every kernel the library launched in the run and divided by the number of
+  steps the run made (each step launches the same kernels once).
 
 Usage::
 
@@ -28,6 +31,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 # sources whose change invalidates a stored traffic measurement of the mark kernel
 MARK_SOURCES = ("csrc/seqcdc_mark.h", "csrc/seqcdc_mark.hip", "csrc/seqcdc_device.h", "csrc/seqcdc_internal.h")
+# kernels of a chunking step (the library's own; uploads and the caller's copies are not counted)
+STEP_KERNELS = ("clear_kernel", "mark_kernel", "chains_kernel", "continue_kernel", "stitch_kernel", "compact_kernel")
 
 
 def source_digest(paths=MARK_SOURCES):
@@ -36,6 +41,12 @@ def source_digest(paths=MARK_SOURCES):
         with open(os.path.join(HERE, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def all_sources_digest():
+    """Digest of every kernel and runtime source: a whole-step measurement holds while none changes."""
+    d = os.path.join(HERE, "csrc")
+    return source_digest(tuple("csrc/" + f for f in sorted(os.listdir(d))))
 
 
 def short_name(name):
@@ -95,6 +106,34 @@ def traffic(fetch_db, write_db, kernel, copy_kernel, copy_bytes):
                             "fetch_scale": sf / 1024.0, "write_scale": sw / 1024.0}}
 
 
+def step_traffic(fetch_db, write_db, steps, copy_kernel, copy_bytes):
+    """HBM bytes of one chunking step: FETCH_SIZE and WRITE_SIZE summed over every dispatch of the step's
+    kernels in each run, divided by `steps`, each counter scaled by the copy kernel's reading; per kernel too."""
+    f = counter_per_dispatch(fetch_db, "FETCH_SIZE")
+    w = counter_per_dispatch(write_db, "WRITE_SIZE")
+
+    def pick(d, name):
+        for k, v in d.items():
+            if name in k:
+                return v
+        raise KeyError("no dispatch of %s (have %s)" % (name, list(d)))
+
+    # the calibration copies are the copy kernel's largest dispatches (small uploads and read-backs also run it)
+    sf = copy_bytes / _median(sorted(pick(f, copy_kernel))[-5:])
+    sw = copy_bytes / _median(sorted(pick(w, copy_kernel))[-5:])
+    per = collections.OrderedDict()
+    for k in STEP_KERNELS:
+        fk = sum(f.get(k, [])) * sf / steps
+        wk = sum(w.get(k, [])) * sw / steps
+        if fk or wk:
+            per[k] = {"fetch_bytes": fk, "write_bytes": wk, "dispatches_per_step": len(f.get(k, [])) / steps}
+    tf = sum(v["fetch_bytes"] for v in per.values())
+    tw = sum(v["write_bytes"] for v in per.values())
+    return {"steps": steps, "fetch_bytes_per_step": tf, "write_bytes_per_step": tw, "bytes_per_step": tf + tw,
+            "per_kernel": per, "calibration": {"copy_kernel": copy_kernel, "copy_bytes": copy_bytes,
+                                               "fetch_scale": sf / 1024.0, "write_scale": sw / 1024.0}}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -114,6 +153,17 @@ def main(argv=None):
     t.add_argument("--cmd-fetch", default="")
     t.add_argument("--cmd-write", default="")
     t.add_argument("--out", required=True)
+    st = sub.add_parser("step")
+    st.add_argument("fetch_db")
+    st.add_argument("write_db")
+    st.add_argument("--steps", type=int, required=True, help="chunking steps the profiled run made")
+    st.add_argument("--workload", required=True)
+    st.add_argument("--input-bytes", type=int, required=True)
+    st.add_argument("--copy-kernel", default="copyBuffer")
+    st.add_argument("--copy-bytes", type=float, required=True)
+    st.add_argument("--cmd-fetch", default="")
+    st.add_argument("--cmd-write", default="")
+    st.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         if a.title:
@@ -124,6 +174,17 @@ def main(argv=None):
         rows = kernel_stats(a.db, a.by_grid)
         for k, c, tot, avg in rows[:a.top] if a.top else rows:
             print("%-40s %8d %14.1f %12.2f" % (k, c, tot / 1e3, avg / 1e3))
+    elif a.cmd == "step":
+        r = step_traffic(a.fetch_db, a.write_db, a.steps, a.copy_kernel, a.copy_bytes)
+        r["workload"] = a.workload
+        r["input_bytes"] = a.input_bytes
+        r["bytes_per_input_byte"] = r["bytes_per_step"] / a.input_bytes
+        r["source_sha256"] = all_sources_digest()
+        r["commands"] = {"fetch": a.cmd_fetch, "write": a.cmd_write}
+        with open(a.out, "w") as f:
+            json.dump(r, f, indent=1)
+        json.dump(r, sys.stdout, indent=1)
+        print()
     else:
         r = traffic(a.fetch_db, a.write_db, a.kernel, a.copy_kernel, a.copy_bytes)
         r["n"] = a.n

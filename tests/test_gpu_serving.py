@@ -84,6 +84,10 @@ def test_serving_matches_oracle_alone_and_in_mix(env):
         adm, passes, peak, peak_n = (ctypes.c_uint64() for _ in range(4))
         seq.lib.seqcdc_server_stats(h, ctypes.byref(adm), ctypes.byref(passes), ctypes.byref(peak),
                                     ctypes.byref(peak_n))
+        tl = seq.seqcdc_server_timeline(h)
+        assert len(tl) == passes.value and sum(r["requests"] for r in tl) == 2 * len(reqs)
+        assert sum(r["bytes"] for r in tl) == 2 * sum(r[2] for r in reqs)
+        assert all(r["gpu_ms"] > 0 and r["layout_ms"] >= 0 and r["retire_ms"] >= 0 for r in tl)
         assert adm.value == 2 * len(reqs)
         assert peak.value <= budget
         assert passes.value < adm.value  # requests were batched together
@@ -130,7 +134,12 @@ def test_serving_concurrent_submitters(env):
 def test_serving_errors(env):
     torch, seq = env
     params = [seq.seqcdc_params_for_avg(8192)]
-    h, keep = _server(seq, params, 4 << 20)
+    arr = (seq.seqcdc_params * 1)(*params)
+    cfg = seq.seqcdc_server_config(0, 64 << 10, 64, 3, 16, 1, arr)  # too small to hold any pass's workspace
+    hh = ctypes.c_void_p()
+    assert seq.lib.seqcdc_server_create(ctypes.byref(cfg), ctypes.byref(hh)) == seq.SEQCDC_EINVAL
+    # 24 MiB over 3 passes: each holds about 5.6 MiB of requests next to its workspace
+    h, keep = _server(seq, params, 24 << 20)
     try:
         t = ctypes.c_uint64()
         buf = torch.zeros(8 << 20, dtype=torch.uint8, device="cuda")
@@ -216,3 +225,36 @@ def test_serving_full_size_requests(env):
     for i, (vi, off, n, pi) in enumerate(reqs):
         want = oracle.chunk(vers[vi][off:off + n], **pd[pi])
         assert out[i].size == want.size and np.array_equal(out[i], want), i
+
+
+def test_serving_submit_many_scheduled(env):
+    """Requests queued by the library at scheduled arrival offsets: each gets its own ticket and the oracle's cuts;
+    a batch with an invalid request queues nothing."""
+    torch, seq = env
+    params = [seq.seqcdc_params_for_avg(8192), seq.seqcdc_params_for_avg(32768)]
+    pd = [dict(mode=p.mode, seq_length=p.seq_length, min_size=p.min_size, max_size=p.max_size,
+               skip_trigger=p.skip_trigger, skip_size=p.skip_size) for p in params]
+    vers, reqs = _requests(60, seed=14, base_len=16 << 20, median=256 << 10, hi=8 << 20)
+    dev_vers = [torch.from_numpy(v).cuda() for v in vers]
+    files = [(dev_vers[vi].data_ptr() + off, n, pi) for vi, off, n, pi in reqs]
+    h, keep = _server(seq, params, 256 << 20)
+    try:
+        bad = files[:3] + [(0, 100, 0)]  # NULL data
+        with pytest.raises(seq.SeqCDCError):
+            seq.seqcdc_server_submit_many(h, bad)
+        at = np.arange(len(files), dtype=np.float64) * 0.05  # one request every 50 us
+        tickets, sub = seq.seqcdc_server_submit_many(h, files, at)
+        assert len(set(int(t) for t in tickets)) == len(files)
+        assert np.all(sub >= at - 1e-6) and np.all(np.diff(sub) >= 0)
+        for i, t in enumerate(tickets):
+            res = seq.seqcdc_result()
+            assert seq.lib.seqcdc_server_wait(h, int(t), 60000.0, ctypes.byref(res)) == 0
+            got = np.ctypeslib.as_array(res.cuts, shape=(res.count,)).copy() if res.count else np.zeros(0, np.uint64)
+            vi, off, n, pi = reqs[i]
+            assert np.array_equal(got, oracle.chunk(vers[vi][off:off + n], **pd[pi])), i
+            assert seq.lib.seqcdc_server_release(h, int(t)) == 0
+        adm = ctypes.c_uint64()
+        seq.lib.seqcdc_server_stats(h, ctypes.byref(adm), None, None, None)
+        assert adm.value == sum(1 for r in reqs if r[2] > 0)  # nothing of the rejected batch was queued
+    finally:
+        seq.lib.seqcdc_server_destroy(h)
