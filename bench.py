@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the other plain variants")
+    ap.add_argument("--no-dedup", action="store_true", help="skip the snapshot-series dedup leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the library's autotuner (default settings)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="oracle work to time on the host")
@@ -396,6 +397,67 @@ def cpu_batched(seq, gpu_counts):
             "counts_match": bool(all(counts[f] == int(gpu_counts[f]) for f in range(nfiles)))}
 
 
+def dedup_leg(seq, torch, stream, steps, warmup, dev):
+    """Config 3: a 256 MiB uniform base and 9 versions of 200 seeded edits, chunked by the batched path at 8 KiB and
+    deduplicated on the device (SHA-256 per chunk, fingerprint table, byte compare); both timed per step."""
+    import synth
+    vers = synth.snapshot_series(256 << 20, 10, seed=0, nedits=200, maxlen=4096)
+    total = sum(v.size for v in vers)
+    log("dedup: %d versions, %.2f GiB" % (len(vers), total / 2 ** 30))
+    devs = [torch.from_numpy(v).to(dev) for v in vers]
+    p = seq.seqcdc_params_for_avg(8192)
+    offs = [0]
+    for v in vers:
+        offs.append(offs[-1] + seq.seqcdc_max_cuts(v.size, p))
+    d_cuts = torch.zeros(offs[-1], dtype=torch.int64, device=dev)
+    d_counts = torch.zeros(len(vers), dtype=torch.int64, device=dev)
+    ftab = seq.file_table([d.data_ptr() for d in devs], [d.numel() for d in devs])
+    otab = seq.offsets_table(offs)
+    plan = seq.seqcdc_plan_create()
+    try:
+        def chunk():
+            seq.seqcdc_chunk_batch(ftab, [p], d_cuts.data_ptr(), otab, d_counts.data_ptr(), stream=stream, plan=plan)
+
+        def dedup():
+            return seq.seqcdc_dedup_batch(plan, ftab, d_cuts.data_ptr(), otab, d_counts.data_ptr(), stream=stream)
+
+        for _ in range(warmup):
+            chunk()
+            res = dedup()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            chunk()
+        torch.cuda.synchronize()
+        cdt = (time.perf_counter() - t0) / steps
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = dedup()
+        ddt = (time.perf_counter() - t0) / steps
+        counts = d_counts.cpu().numpy()
+        allc = d_cuts.cpu().numpy().astype(np.uint64)
+    finally:
+        seq.seqcdc_plan_destroy(plan)
+    cuts = [allc[offs[i]:offs[i] + int(counts[i])] for i in range(len(vers))]
+    orig, uniq = res
+    return {"versions": len(vers), "bytes": total, "chunks": int(counts.sum()), "chunk_ms": round(cdt * 1e3, 3),
+            "chunk_GBps": round(total / cdt / 1e9, 1), "dedup_ms": round(ddt * 1e3, 3),
+            "dedup_GBps": round(total / ddt / 1e9, 1), "orig_bytes": orig, "unique_bytes": uniq,
+            "savings": round((orig - uniq) / orig, 6), "_check": (vers, cuts, p)}
+
+
+def dedup_parity(check, orig, uniq):
+    """The oracle's chunking and Eq. 1 over the same series (host side, after the GPU measurements)."""
+    import oracle
+    vers, cuts, p = check
+    kw = dict(mode=p.mode, seq_length=p.seq_length, min_size=p.min_size, max_size=p.max_size,
+              skip_trigger=p.skip_trigger, skip_size=p.skip_size)
+    want = [oracle.chunk(v, **kw) for v in vers]
+    same_cuts = all(np.array_equal(a, b) for a, b in zip(cuts, want))
+    o2, u2, _, _ = oracle.dedup_stats(vers, want)
+    return bool(same_cuts and (orig, uniq) == (o2, u2))
+
+
 def serving_parity(checks):
     """Every request of the saturated serving run against the oracle on its own bytes (host side, after the GPU
     measurements)."""
@@ -550,6 +612,9 @@ def main():
     if not args.no_serve:
         extra["serving"] = serving(seq, torch, dev)
         log("serving: %s" % {k: v for k, v in extra["serving"].items() if k != "_checks"})
+    if not args.no_dedup:
+        extra["dedup"] = dedup_leg(seq, torch, stream, args.steps, args.warmup, dev)
+        log("dedup: %s" % {k: v for k, v in extra["dedup"].items() if k != "_check"})
     if not args.no_sweep:  # last: its autotuning sets the process-wide choices of more parameter classes
         extra["sweep"] = sweep(seq, torch, stream, d, args.steps, not args.no_tune)
         log("sweep: %s" % extra["sweep"])
@@ -566,6 +631,10 @@ def main():
         if "serving" in extra:
             extra["serving"]["parity_vs_oracle"] = serving_parity(extra["serving"]["_checks"])
             log("serving parity %s" % extra["serving"]["parity_vs_oracle"])
+        if "dedup" in extra:
+            extra["dedup"]["parity_vs_oracle"] = dedup_parity(extra["dedup"]["_check"], extra["dedup"]["orig_bytes"],
+                                                              extra["dedup"]["unique_bytes"])
+            log("dedup parity %s" % extra["dedup"]["parity_vs_oracle"])
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True, "scaling": "weak",
@@ -578,6 +647,8 @@ def main():
         extra["batched"].pop("counts", None)
     if "serving" in extra:
         extra["serving"].pop("_checks", None)
+    if "dedup" in extra:
+        extra["dedup"].pop("_check", None)
     out.update(extra)
     print(json.dumps(out), flush=True)
     seq.seqcdc_plan_destroy(plan)

@@ -242,6 +242,26 @@ int seqcdc_dedup_stats(const uint8_t* const* h_buffers, const uint64_t* const* h
                        uint32_t nbuffers, uint64_t* orig_bytes, uint64_t* unique_bytes, double* savings,
                        double* ratio);
 
+/* Deduplication on the device, the stage after chunking (Sec. II, Eq. 1):
+ * the chunks of many device-resident files, laid out as seqcdc_chunk_batch
+ * writes them (file f's cuts at d_cuts[h_cut_offsets[f] ..], d_counts[f] of
+ * them, chunk i = [cut i-1, cut i) with cut -1 = 0), are fingerprinted with
+ * SHA-256 (FIPS 180-4), entered into an open-addressing table of
+ * fingerprints, and every chunk whose fingerprint is already in the table is
+ * compared byte for byte with the chunk that holds the entry.  Outputs: the
+ * original bytes (all chunks) and the unique bytes (chunks that are not a
+ * byte-for-byte copy of an earlier entry), so savings = (orig - unique) /
+ * orig and ratio = orig / unique.  d_digests (may be NULL): receives the
+ * fingerprint of the chunk in cut slot s at d_digests[8 (s - h_cut_offsets[0])
+ * ..], eight 32-bit words, word 0 first, each the big-endian word of the
+ * standard's digest (slots past a file's count get zeros).  The plan provides
+ * the workspace (the table has at least twice as many entries as cut slots)
+ * and must not be used by another call at the same time.  seqcdc_file's
+ * params_index is ignored.  Synchronous. */
+int seqcdc_dedup_batch(seqcdc_plan* plan, const seqcdc_file* h_files, uint32_t nfiles, const uint64_t* d_cuts,
+                       const uint64_t* h_cut_offsets, const uint64_t* d_counts, uint32_t* d_digests,
+                       uint64_t* h_orig, uint64_t* h_unique, void* stream);
+
 /* ---------------------------------------------------------------------
  * Serving: a dedup-ingest request loop with continuous batching.
  * Requests reference device-resident bytes.  The memory budget is split

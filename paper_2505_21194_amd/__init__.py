@@ -98,6 +98,8 @@ _SIGS = {
     "seqcdc_dedup_stats": ([ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_u64), _u32,
                             ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_double),
                             ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "seqcdc_dedup_batch": ([_p, ctypes.POINTER(seqcdc_file), _u32, _p, ctypes.POINTER(_u64), _p, _p,
+                            ctypes.POINTER(_u64), ctypes.POINTER(_u64), _p], ctypes.c_int),
     "seqcdc_server_create": ([ctypes.POINTER(seqcdc_server_config), ctypes.POINTER(_p)], ctypes.c_int),
     "seqcdc_server_submit": ([_p, _p, _u64, _u32, ctypes.POINTER(_u64)], ctypes.c_int),
     "seqcdc_server_submit_many": ([_p, ctypes.POINTER(seqcdc_file), _u32, ctypes.POINTER(ctypes.c_double),
@@ -352,6 +354,21 @@ def seqcdc_dedup_stats(buffers, cut_lists):
     _check(lib.seqcdc_dedup_stats(bp, cp, cnt, nb, ctypes.byref(o), ctypes.byref(u), ctypes.byref(s),
                                   ctypes.byref(r)))
     return o.value, u.value, s.value, r.value
+
+
+def seqcdc_dedup_batch(plan, files, d_cuts, cut_offsets, d_counts, d_digests=None, stream=None):
+    """Device deduplication of chunked files (Eq. 1): returns (original bytes, unique bytes).  files: a
+    file_table() or a list of (device_ptr, n, params_index)."""
+    if isinstance(files, ctypes.Array):
+        farr, nf = files, getattr(files, "_len", len(files))
+    else:
+        farr = file_table([f[0] for f in files], [f[1] for f in files], [f[2] for f in files])
+        nf = len(files)
+    offs = cut_offsets if isinstance(cut_offsets, ctypes.Array) else offsets_table(cut_offsets)
+    o, u = _u64(), _u64()
+    _check(lib.seqcdc_dedup_batch(plan, farr, nf, d_cuts, offs, d_counts, d_digests, ctypes.byref(o),
+                                  ctypes.byref(u), _stream_handle(stream)))
+    return o.value, u.value
 
 
 # ------------------------------------------------------------------ torch conveniences

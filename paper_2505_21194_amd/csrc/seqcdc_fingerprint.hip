@@ -1,0 +1,383 @@
+// Deduplication on the device, the stage after chunking (Sec. II): every
+// chunk gets a SHA-256 fingerprint, fingerprints go into an open-addressing
+// table, and a chunk whose fingerprint is already there is compared byte for
+// byte with the chunk that holds the entry.  The space savings of Eq. 1 follow
+// from the bytes of the chunks that are not duplicates.
+//
+// SHA-256 is FIPS 180-4: 512-bit blocks, the message padded with a 1 bit,
+// zeros and its 64-bit bit length, eight 32-bit working variables, 64 rounds
+// per block.  One thread hashes one chunk (the blocks of a message are
+// sequential); a chunk's bytes are read as aligned 32-bit words realigned to
+// its first byte, so any chunk start works.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "../../include/seqcdc.h"
+#include "seqcdc_device.h"
+#include "seqcdc_runtime.h"
+
+namespace seqcdc {
+
+// FIPS 180-4 Sec. 4.2.2: the first 32 bits of the fractional parts of the
+// cube roots of the first 64 primes.
+__constant__ u32 kSha256K[64] = {
+    0x428a2f98u, 0x71374491u, 0xb5c0fbcfu, 0xe9b5dba5u, 0x3956c25bu, 0x59f111f1u, 0x923f82a4u, 0xab1c5ed5u,
+    0xd807aa98u, 0x12835b01u, 0x243185beu, 0x550c7dc3u, 0x72be5d74u, 0x80deb1feu, 0x9bdc06a7u, 0xc19bf174u,
+    0xe49b69c1u, 0xefbe4786u, 0x0fc19dc6u, 0x240ca1ccu, 0x2de92c6fu, 0x4a7484aau, 0x5cb0a9dcu, 0x76f988dau,
+    0x983e5152u, 0xa831c66du, 0xb00327c8u, 0xbf597fc7u, 0xc6e00bf3u, 0xd5a79147u, 0x06ca6351u, 0x14292967u,
+    0x27b70a85u, 0x2e1b2138u, 0x4d2c6dfcu, 0x53380d13u, 0x650a7354u, 0x766a0abbu, 0x81c2c92eu, 0x92722c85u,
+    0xa2bfe8a1u, 0xa81a664bu, 0xc24b8b70u, 0xc76c51a3u, 0xd192e819u, 0xd6990624u, 0xf40e3585u, 0x106aa070u,
+    0x19a4c116u, 0x1e376c08u, 0x2748774cu, 0x34b0bcb5u, 0x391c0cb3u, 0x4ed8aa4au, 0x5b9cca4fu, 0x682e6ff3u,
+    0x748f82eeu, 0x78a5636fu, 0x84c87814u, 0x8cc70208u, 0x90befffau, 0xa4506cebu, 0xbef9a3f7u, 0xc67178f2u};
+
+// FIPS 180-4 Sec. 5.3.3: the first 32 bits of the fractional parts of the
+// square roots of the first 8 primes.
+constexpr u32 kSha256H0[8] = {0x6a09e667u, 0xbb67ae85u, 0x3c6ef372u, 0xa54ff53au,
+                              0x510e527fu, 0x9b05688cu, 0x1f83d9abu, 0x5be0cd19u};
+
+__device__ __forceinline__ u32 rotr(u32 x, u32 n) { return __builtin_amdgcn_alignbit(x, x, n); }
+__device__ __forceinline__ u32 bswap32(u32 x) { return __builtin_amdgcn_perm(0u, x, 0x00010203u); }
+
+// One 64-byte block into the state (FIPS 180-4 Sec. 6.2.2), the message
+// schedule kept as a rolling window of 16 words.
+__device__ __forceinline__ void sha256_block(u32 st[8], u32 w[16]) {
+  u32 a = st[0], b = st[1], c = st[2], d = st[3], e = st[4], f = st[5], g = st[6], h = st[7];
+#pragma unroll
+  for (int i = 0; i < 64; i++) {
+    u32 wi;
+    if (i < 16) {
+      wi = w[i];
+    } else {
+      const u32 w15 = w[(i - 15) & 15], w2 = w[(i - 2) & 15];
+      const u32 s0 = rotr(w15, 7) ^ rotr(w15, 18) ^ (w15 >> 3);
+      const u32 s1 = rotr(w2, 17) ^ rotr(w2, 19) ^ (w2 >> 10);
+      wi = w[i & 15] + s0 + w[(i - 7) & 15] + s1;
+      w[i & 15] = wi;
+    }
+    const u32 S1 = rotr(e, 6) ^ rotr(e, 11) ^ rotr(e, 25);
+    const u32 ch = (e & f) ^ (~e & g);
+    const u32 t1 = h + S1 + ch + kSha256K[i] + wi;
+    const u32 S0 = rotr(a, 2) ^ rotr(a, 13) ^ rotr(a, 22);
+    const u32 maj = (a & b) ^ (a & c) ^ (b & c);
+    const u32 t2 = S0 + maj;
+    h = g;
+    g = f;
+    f = e;
+    e = d + t1;
+    d = c;
+    c = b;
+    b = a;
+    a = t1 + t2;
+  }
+  st[0] += a;
+  st[1] += b;
+  st[2] += c;
+  st[3] += d;
+  st[4] += e;
+  st[5] += f;
+  st[6] += g;
+  st[7] += h;
+}
+
+// The 16 big-endian message words of the 64 bytes at p (p + 64 <= end), or
+// of the last part of a message: the bytes [p, end) followed, when `pad`, by
+// the 0x80 byte at end - p (< 64) and zeros.  Only aligned words that hold a
+// byte below `end` are read: such a word never crosses a page end.
+__device__ __forceinline__ void load_words(const uint8_t* p, const uint8_t* end, bool pad, u32 w[16]) {
+  const uintptr_t a = (uintptr_t)p;
+  const u32 sh = (u32)(a & 3);
+  const SEQCDC_GLOBAL u32* base = as_global((const u32*)(a - sh));
+  const uintptr_t e = (uintptr_t)end;
+  u32 d[17];
+#pragma unroll
+  for (int j = 0; j < 17; j++) d[j] = (a - sh + 4 * j < e) ? base[j] : 0u;
+  const u32 valid = e - a < 64 ? (u32)(e - a) : 64u;
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    u32 x = __builtin_amdgcn_alignbyte(d[k + 1], d[k], sh);  // bytes 4k .. 4k+3 from p, little-endian
+    const u32 o = 4 * k;
+    if (o + 4 > valid) {  // the word holds the end of the message
+      const u32 keep = valid > o ? valid - o : 0;  // 0..3 message bytes
+      x = keep ? x & ((1u << (8 * keep)) - 1u) : 0u;
+      if (pad && valid >= o && valid < o + 4) x |= 0x80u << (8 * (valid - o));
+    }
+    w[k] = bswap32(x);
+  }
+}
+
+// SHA-256 of the len bytes at p.
+__device__ void sha256(const uint8_t* p, u64 len, u32 out[8]) {
+  u32 st[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) st[i] = kSha256H0[i];
+  const uint8_t* end = p + len;
+  u32 w[16];
+  u64 full = len >> 6;
+  for (u64 b = 0; b < full; b++) {
+    load_words(p + 64 * b, end, false, w);
+    sha256_block(st, w);
+  }
+  // the rest of the message, the 0x80 byte and the 64-bit bit length
+  const u32 rest = (u32)(len & 63);
+  load_words(p + 64 * full, end, true, w);
+  if (rest >= 56) {  // no room for the length in this block
+    sha256_block(st, w);
+#pragma unroll
+    for (int k = 0; k < 16; k++) w[k] = 0;
+  }
+  w[14] = (u32)((len * 8) >> 32);
+  w[15] = (u32)(len * 8);
+  sha256_block(st, w);
+#pragma unroll
+  for (int i = 0; i < 8; i++) out[i] = st[i];
+}
+
+// The 16 bytes at p + off .. (fewer where the chunk [p, p + len) ends; the
+// rest is zero) as 4 little-endian words, read as aligned words that each hold
+// a byte of the chunk.
+__device__ __forceinline__ void load16_chunk(const uint8_t* p, u64 len, u64 off, u32 out[4]) {
+  const uintptr_t a = (uintptr_t)(p + off);
+  const u32 sh = (u32)(a & 3);
+  const SEQCDC_GLOBAL u32* base = as_global((const u32*)(a - sh));
+  const uintptr_t e = (uintptr_t)(p + len);
+  u32 d[5];
+#pragma unroll
+  for (int j = 0; j < 5; j++) d[j] = (a - sh + 4 * j < e) ? base[j] : 0u;
+  const u64 left = len > off ? len - off : 0;
+  const u32 valid = left < 16 ? (u32)left : 16u;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    u32 x = __builtin_amdgcn_alignbyte(d[k + 1], d[k], sh);
+    const u32 o = 4 * k;
+    if (o + 4 > valid) x = valid > o ? x & ((1u << (8 * (valid - o))) - 1u) : 0u;
+    out[k] = x;
+  }
+}
+
+// A file of the call: its bytes, the range of its cut slots, its count.
+struct DedupFile {
+  const uint8_t* data;
+  u64 slot0;               // first slot (index into d_cuts / digests)
+  const u64* count;        // device: number of cuts
+};
+
+__device__ __forceinline__ u32 file_of_slot(const DedupFile* __restrict__ files, u32 nfiles, u64 slot) {
+  u32 lo = 0, hi = nfiles;  // last file with slot0 <= slot
+  while (hi - lo > 1) {
+    const u32 mid = (lo + hi) >> 1;
+    if (files[mid].slot0 <= slot) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Chunk `slot`: its file's bytes and [start, end); false for a slot past the file's count.
+__device__ __forceinline__ bool chunk_of(const DedupFile* __restrict__ files, u32 nfiles, const u64* __restrict__ cuts,
+                                         u64 slot, const uint8_t*& data, u64& start, u64& end) {
+  const DedupFile& F = files[file_of_slot(files, nfiles, slot)];
+  const u64 j = slot - F.slot0;
+  if (j >= *F.count) return false;
+  data = F.data;
+  start = j ? cuts[slot - 1] : 0;
+  end = cuts[slot];
+  return true;
+}
+
+// Pass 1: the fingerprint of every chunk (one thread each).
+__global__ __launch_bounds__(256) void sha_kernel(const DedupFile* __restrict__ files, u32 nfiles,
+                                                  const u64* __restrict__ cuts, u64 nslots, u32* digests) {
+  const u64 slot = (u64)blockIdx.x * 256 + threadIdx.x;
+  if (slot >= nslots) return;
+  const uint8_t* data;
+  u64 start, end;
+  u32 h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (chunk_of(files, nfiles, cuts, slot, data, start, end)) sha256(data + start, end - start, h);
+  uint4* dst = (uint4*)(digests + 8 * slot);
+  dst[0] = make_uint4(h[0], h[1], h[2], h[3]);
+  dst[1] = make_uint4(h[4], h[5], h[6], h[7]);
+}
+
+constexpr u32 kNoOwner = 0xFFFFFFFFu;
+
+// Pass 2: every chunk enters the table of 2^k 64-bit entries (tag: the
+// digest's first word; value: slot + 1), probing linearly from its second
+// word.  A chunk that finds an entry with its full digest records that
+// entry's slot as its owner; the others own their entry.
+__global__ __launch_bounds__(256) void insert_kernel(const DedupFile* __restrict__ files, u32 nfiles,
+                                                     const u64* __restrict__ cuts, u64 nslots,
+                                                     const u32* __restrict__ digests, u64* table, u64 mask,
+                                                     u32* owner) {
+  const u64 slot = (u64)blockIdx.x * 256 + threadIdx.x;
+  if (slot >= nslots) return;
+  const uint8_t* data;
+  u64 start, end;
+  if (!chunk_of(files, nfiles, cuts, slot, data, start, end)) {
+    owner[slot] = kNoOwner;
+    return;
+  }
+  const u32* h = digests + 8 * slot;
+  const u64 entry = ((u64)h[0] << 32) | (u64)(slot + 1);
+  u64 pos = h[1] & mask;
+  for (u64 probe = 0; probe <= mask; probe++, pos = (pos + 1) & mask) {
+    const u64 prev = atomicCAS((unsigned long long*)&table[pos], 0ull, (unsigned long long)entry);
+    if (prev == 0) {  // the entry is this chunk's
+      owner[slot] = kNoOwner;
+      return;
+    }
+    if ((u32)(prev >> 32) != h[0]) continue;
+    const u64 other = (prev & 0xFFFFFFFFull) - 1;
+    const u32* g = digests + 8 * other;
+    bool same = true;
+#pragma unroll
+    for (int i = 1; i < 8; i++) same = same && g[i] == h[i];
+    if (same) {
+      owner[slot] = (u32)other;
+      return;
+    }
+  }
+  owner[slot] = kNoOwner;  // unreachable: the table has more entries than chunks
+}
+
+// Pass 3: one wave per chunk.  A chunk with no owner is unique; a chunk with
+// an owner is a duplicate if the two have the same length and bytes (checked
+// 16 bytes per lane at a time).  The bytes of the unique chunks and of all
+// chunks are added up per workgroup, then into the totals.
+__global__ __launch_bounds__(256) void verify_kernel(const DedupFile* __restrict__ files, u32 nfiles,
+                                                     const u64* __restrict__ cuts, u64 nslots,
+                                                     const u32* __restrict__ owner, u64* totals) {
+  __shared__ u64 s_orig[kWavesPerGroup], s_uniq[kWavesPerGroup];
+  const u32 lane = lane_id();
+  const u32 wv = threadIdx.x >> 6;
+  const u64 slot = (u64)blockIdx.x * kWavesPerGroup + __builtin_amdgcn_readfirstlane(wv);
+  u64 orig = 0, uniq = 0;
+  const uint8_t* data;
+  u64 start, end;
+  if (slot < nslots && chunk_of(files, nfiles, cuts, slot, data, start, end)) {
+    const u64 len = end - start;
+    orig = len;
+    const u32 o = owner[slot];
+    bool dup = false;
+    if (o != kNoOwner) {
+      const uint8_t* odata;
+      u64 ostart, oend;
+      chunk_of(files, nfiles, cuts, o, odata, ostart, oend);
+      dup = oend - ostart == len;
+      const uint8_t* pa = data + start;
+      const uint8_t* pb = odata + ostart;
+      for (u64 base = 0; dup && base < len; base += 1024) {
+        const u64 off = base + 16ull * lane;
+        u32 va[4], vb[4];
+        load16_chunk(pa, len, off, va);
+        load16_chunk(pb, len, off, vb);
+        const bool eq = va[0] == vb[0] && va[1] == vb[1] && va[2] == vb[2] && va[3] == vb[3];
+        dup = ballot(!eq) == 0;
+      }
+    }
+    uniq = dup ? 0 : len;
+  }
+  if (lane == 0) {
+    s_orig[wv] = orig;
+    s_uniq[wv] = uniq;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u64 so = 0, su = 0;
+    for (u32 i = 0; i < kWavesPerGroup; i++) {
+      so += s_orig[i];
+      su += s_uniq[i];
+    }
+    if (so) atomicAdd((unsigned long long*)&totals[0], (unsigned long long)so);
+    if (su) atomicAdd((unsigned long long*)&totals[1], (unsigned long long)su);
+  }
+}
+
+__global__ __launch_bounds__(256) void zero64_kernel(u64* p, u64 count) {
+  for (u64 i = (u64)blockIdx.x * 256 + threadIdx.x; i < count; i += (u64)gridDim.x * 256) p[i] = 0;
+}
+
+}  // namespace seqcdc
+
+using namespace seqcdc;
+
+extern "C" int seqcdc_dedup_batch(seqcdc_plan* plan, const seqcdc_file* h_files, uint32_t nfiles,
+                                  const uint64_t* d_cuts, const uint64_t* h_cut_offsets, const uint64_t* d_counts,
+                                  uint32_t* d_digests, uint64_t* h_orig, uint64_t* h_unique, void* stream) {
+  if (!plan || !h_files || !h_cut_offsets || !d_counts || !h_orig || !h_unique)
+    return fail(SEQCDC_EINVAL, "NULL argument");
+  if (nfiles == 0) {
+    *h_orig = *h_unique = 0;
+    return SEQCDC_OK;
+  }
+  if (!d_cuts) return fail(SEQCDC_EINVAL, "NULL cut array");
+  for (u32 f = 0; f < nfiles; f++) {
+    if (h_cut_offsets[f + 1] < h_cut_offsets[f]) return fail(SEQCDC_EINVAL, "cut offsets must not decrease");
+    if (h_files[f].n && !h_files[f].d_data) return fail(SEQCDC_EINVAL, "file %u: NULL data", f);
+  }
+  const u64 slot0 = h_cut_offsets[0];
+  const u64 nslots = h_cut_offsets[nfiles] - slot0;
+  if (nslots >= 0xFFFFFFFEull) return fail(SEQCDC_EINVAL, "too many cut slots");
+  Plan* pl = (Plan*)plan;
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> g(pl->mu);
+  hipError_t e = hipSetDevice(pl->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if (pl->pending && pl->last_stream != st) {
+    e = hipStreamWaitEvent(st, pl->call_done, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+  }
+  u64 cap = 1024;
+  while (cap < 2 * nslots) cap <<= 1;
+  int rc;
+  std::vector<DedupFile> df(nfiles);
+  for (u32 f = 0; f < nfiles; f++)
+    df[f] = DedupFile{(const uint8_t*)h_files[f].d_data, h_cut_offsets[f] - slot0, d_counts + f};
+  const size_t files_bytes = (nfiles * sizeof(DedupFile) + 255) & ~(size_t)255;
+  const size_t dig_bytes = d_digests ? 0 : ((nslots * 32 + 255) & ~(size_t)255);
+  const size_t owner_bytes = (nslots * 4 + 255) & ~(size_t)255;
+  const size_t table_bytes = cap * 8;
+  const size_t total = files_bytes + dig_bytes + owner_bytes + table_bytes + 256;
+  if ((rc = pl->misc.reserve(total))) return rc;
+  if ((rc = pl->readback.reserve(64))) return rc;
+  char* base = (char*)pl->misc.p;
+  DedupFile* d_files = (DedupFile*)base;
+  u32* digests = d_digests ? d_digests : (u32*)(base + files_bytes);
+  u32* owner = (u32*)(base + files_bytes + dig_bytes);
+  u64* table = (u64*)(base + files_bytes + dig_bytes + owner_bytes);
+  u64* totals = (u64*)(base + files_bytes + dig_bytes + owner_bytes + table_bytes);
+  if ((rc = pl->staging.reserve(files_bytes))) return rc;
+  if (pl->upload_pending) {
+    e = hipEventSynchronize(pl->upload_done);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    pl->upload_pending = false;
+  }
+  memcpy(pl->staging.p, df.data(), nfiles * sizeof(DedupFile));
+  pl->uploaded_dev = nullptr;  // the table buffer no longer holds a chunking call's tables
+  e = hipMemcpyAsync(d_files, pl->staging.p, nfiles * sizeof(DedupFile), hipMemcpyHostToDevice, st);
+  const u64* cuts = d_cuts + slot0;
+  const u32 grid = (u32)((nslots + 255) / 256);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(zero64_kernel, dim3(1024), dim3(256), 0, st, table, cap + 2);
+    hipLaunchKernelGGL(zero64_kernel, dim3(1), dim3(256), 0, st, totals, (u64)2);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && nslots) {
+    hipLaunchKernelGGL(sha_kernel, dim3(grid), dim3(256), 0, st, d_files, nfiles, cuts, nslots, digests);
+    hipLaunchKernelGGL(insert_kernel, dim3(grid), dim3(256), 0, st, d_files, nfiles, cuts, nslots,
+                       (const u32*)digests, table, cap - 1, owner);
+    hipLaunchKernelGGL(verify_kernel, dim3((u32)((nslots + kWavesPerGroup - 1) / kWavesPerGroup)), dim3(256), 0, st,
+                       d_files, nfiles, cuts, nslots, (const u32*)owner, totals);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(pl->readback.p, totals, 16, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "seqcdc_dedup_batch");
+  pl->pending = false;
+  const u64* r = (const u64*)pl->readback.p;
+  *h_orig = r[0];
+  *h_unique = r[1];
+  return SEQCDC_OK;
+}

@@ -125,6 +125,20 @@ def test_snapshot_series_full(env, snapshots, avg_kib):
     ref = oracle.dedup_stats(vers, want)
     assert got[0] == ref[0] and got[1] == ref[1]
     assert got[2] == pytest.approx(ref[2], abs=1e-12) and got[3] == pytest.approx(ref[3], rel=1e-12)
+    # the same series chunked and deduplicated on the device (fingerprints, table, byte compare)
+    plan = seq.seqcdc_plan_create()
+    try:
+        offs = [0]
+        for v in vers:
+            offs.append(offs[-1] + seq.seqcdc_max_cuts(v.size, p))
+        d_cuts = torch.zeros(offs[-1], dtype=torch.int64, device="cuda")
+        d_counts = torch.zeros(len(vers), dtype=torch.int64, device="cuda")
+        files = [(d.data_ptr(), d.numel(), 0) for d in devs]
+        seq.seqcdc_chunk_batch(files, [p], d_cuts.data_ptr(), offs, d_counts.data_ptr(), plan=plan)
+        dev = seq.seqcdc_dedup_batch(plan, files, d_cuts.data_ptr(), offs, d_counts.data_ptr())
+    finally:
+        seq.seqcdc_plan_destroy(plan)
+    assert dev == (ref[0], ref[1])
 
 
 def test_batched_4096_files(env, direct_plan):
