@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the other plain variants")
     ap.add_argument("--no-dedup", action="store_true", help="skip the snapshot-series dedup leg")
+    ap.add_argument("--no-calib", action="store_true", help="skip the calibration leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the library's autotuner (default settings)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="oracle work to time on the host")
@@ -446,6 +447,37 @@ def dedup_leg(seq, torch, stream, steps, warmup, dev):
             "savings": round((orig - uniq) / orig, 6), "_check": (vers, cuts, p)}
 
 
+def calibration_leg(seq, torch, stream, dev):
+    """Monte-Carlo calibration (Sec. V) on 256 MiB of uniform bytes: a grid of 70 candidates (SeqLength 5 and 6 x 7
+    triggers x 5 skip sizes, min = 4 KiB, max = 16 KiB) for an 8 KiB target in one call, and the Table I parameter
+    sets at 4 / 8 / 16 KiB for both SeqLength readings."""
+    import synth
+    n = 256 << 20
+    d = torch.from_numpy(synth.uniform(n, seed=29)).to(dev)
+    plan = seq.seqcdc_plan_create()
+    try:
+        seq.calibrate_for_avg(plan, d.data_ptr(), n, 8192, stream=stream)  # warm-up (workspace)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        best, st, grid = seq.calibrate_for_avg(plan, d.data_ptr(), n, 8192, stream=stream)
+        dt = time.perf_counter() - t0
+        rows = [(4096, 1024, 55, 256), (8192, 4096, 50, 256), (16384, 8192, 50, 512)]
+        table1 = {}
+        for sl in (5, 6):
+            cands = [dict(mode=0, seq_length=sl, min_size=mn, max_size=2 * avg, skip_trigger=t, skip_size=k)
+                     for avg, mn, t, k in rows]
+            table1["seq_length_%d" % sl] = [round(x["mean"], 1) for x in seq.seqcdc_calibrate(plan, d.data_ptr(), n,
+                                                                                               cands, stream=stream)]
+    finally:
+        seq.seqcdc_plan_destroy(plan)
+    return {"sample_bytes": n, "candidates": len(grid), "ms": round(dt * 1e3, 3),
+            "GBps": round(len(grid) * n / dt / 1e9, 1),
+            "best_for_8KiB": {"seq_length": best.seq_length, "skip_trigger": best.skip_trigger,
+                              "skip_size": best.skip_size, "mean": round(st["mean"], 1),
+                              "max_share": round(st["max_chunks"] / max(st["chunks"], 1), 4)},
+            "table1_means_4_8_16KiB": table1}
+
+
 def dedup_parity(check, orig, uniq):
     """The oracle's chunking and Eq. 1 over the same series (host side, after the GPU measurements)."""
     import oracle
@@ -615,6 +647,9 @@ def main():
     if not args.no_dedup:
         extra["dedup"] = dedup_leg(seq, torch, stream, args.steps, args.warmup, dev)
         log("dedup: %s" % {k: v for k, v in extra["dedup"].items() if k != "_check"})
+    if not args.no_calib:
+        extra["calibration"] = calibration_leg(seq, torch, stream, dev)
+        log("calibration: %s" % extra["calibration"])
     if not args.no_sweep:  # last: its autotuning sets the process-wide choices of more parameter classes
         extra["sweep"] = sweep(seq, torch, stream, d, args.steps, not args.no_tune)
         log("sweep: %s" % extra["sweep"])

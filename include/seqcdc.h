@@ -242,6 +242,22 @@ int seqcdc_dedup_stats(const uint8_t* const* h_buffers, const uint64_t* const* h
                        uint32_t nbuffers, uint64_t* orig_bytes, uint64_t* unique_bytes, double* savings,
                        double* ratio);
 
+/* Monte-Carlo calibration (Sec. V, Table I): the paper chooses SeqLength,
+ * SkipTrigger and SkipSize so that random data gives the target average chunk
+ * size.  seqcdc_calibrate chunks the device-resident sample (n bytes, normally
+ * uniform random bytes the caller generated) under each of the ncand candidate
+ * parameter sets, all in one batched call, and reduces each candidate's chunk
+ * statistics on the device into out[i].  Synchronous; uses the plan's
+ * workspace (about 8 x n / min_size bytes per candidate for the cut lists). */
+typedef struct {
+  uint64_t chunks;     /* chunks of the sample (the last one included) */
+  uint64_t max_chunks; /* chunks cut at max_size, the last chunk not counted */
+  double mean;         /* n / chunks */
+  double stddev;       /* of the chunk lengths */
+} seqcdc_calib_stats;
+int seqcdc_calibrate(seqcdc_plan* plan, const void* d_sample, uint64_t n, const seqcdc_params* cands, uint32_t ncand,
+                     seqcdc_calib_stats* out, void* stream);
+
 /* Deduplication on the device, the stage after chunking (Sec. II, Eq. 1):
  * the chunks of many device-resident files, laid out as seqcdc_chunk_batch
  * writes them (file f's cuts at d_cuts[h_cut_offsets[f] ..], d_counts[f] of

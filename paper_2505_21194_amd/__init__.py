@@ -50,6 +50,10 @@ class seqcdc_result(ctypes.Structure):
                 ("latency_ms", ctypes.c_double), ("queue_ms", ctypes.c_double)]
 
 
+class seqcdc_calib_stats(ctypes.Structure):
+    _fields_ = [("chunks", _u64), ("max_chunks", _u64), ("mean", ctypes.c_double), ("stddev", ctypes.c_double)]
+
+
 class seqcdc_pass_record(ctypes.Structure):
     _fields_ = [("requests", _u32), ("grew", _u32), ("bytes", _u64), ("wait_ms", ctypes.c_double),
                 ("layout_ms", ctypes.c_double), ("gpu_ms", ctypes.c_double), ("retire_ms", ctypes.c_double)]
@@ -98,6 +102,8 @@ _SIGS = {
     "seqcdc_dedup_stats": ([ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_u64), _u32,
                             ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_double),
                             ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "seqcdc_calibrate": ([_p, _p, _u64, ctypes.POINTER(seqcdc_params), _u32, ctypes.POINTER(seqcdc_calib_stats), _p],
+                         ctypes.c_int),
     "seqcdc_dedup_batch": ([_p, ctypes.POINTER(seqcdc_file), _u32, _p, ctypes.POINTER(_u64), _p, _p,
                             ctypes.POINTER(_u64), ctypes.POINTER(_u64), _p], ctypes.c_int),
     "seqcdc_server_create": ([ctypes.POINTER(seqcdc_server_config), ctypes.POINTER(_p)], ctypes.c_int),
@@ -354,6 +360,28 @@ def seqcdc_dedup_stats(buffers, cut_lists):
     _check(lib.seqcdc_dedup_stats(bp, cp, cnt, nb, ctypes.byref(o), ctypes.byref(u), ctypes.byref(s),
                                   ctypes.byref(r)))
     return o.value, u.value, s.value, r.value
+
+
+def seqcdc_calibrate(plan, d_sample, n, candidates, stream=None):
+    """Chunk statistics of each candidate parameter set on a device-resident sample: a list of dicts (chunks,
+    max_chunks, mean, stddev)."""
+    cands = [_as_params(p) for p in candidates]
+    arr = (seqcdc_params * max(len(cands), 1))(*cands)
+    out = (seqcdc_calib_stats * max(len(cands), 1))()
+    _check(lib.seqcdc_calibrate(plan, d_sample, n, arr, len(cands), out, _stream_handle(stream)))
+    return [{k: getattr(out[i], k) for k, _ in seqcdc_calib_stats._fields_} for i in range(len(cands))]
+
+
+def calibrate_for_avg(plan, d_sample, n, target_avg, seq_lengths=(5, 6), triggers=(25, 35, 45, 50, 55, 65, 80),
+                      skips=(128, 256, 384, 512, 768), stream=None):
+    """The candidate closest to a target average chunk size on the sample (Sec. V): a grid over SeqLength,
+    SkipTrigger and SkipSize with min = target/2 and max = 2 x target (Sec. VI), evaluated in one call.  Returns
+    (best params, its stats, all (params, stats) pairs)."""
+    grid = [make_params(0, sl, max(target_avg // 2, sl), 2 * target_avg, t, k)
+            for sl in seq_lengths for t in triggers for k in skips]
+    stats = seqcdc_calibrate(plan, d_sample, n, grid, stream=stream)
+    best = min(range(len(grid)), key=lambda i: abs(stats[i]["mean"] - target_avg))
+    return grid[best], stats[best], list(zip(grid, stats))
 
 
 def seqcdc_dedup_batch(plan, files, d_cuts, cut_offsets, d_counts, d_digests=None, stream=None):

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libseqcdc.so")
-SOURCES = ["seqcdc_mark.hip", "seqcdc_resolve.hip", "seqcdc_api.cpp", "seqcdc_autotune.cpp", "seqcdc_dedup.cpp", "seqcdc_server.cpp", "seqcdc_graph.cpp", "seqcdc_noalloc.hip", "seqcdc_fingerprint.hip"]
+SOURCES = ["seqcdc_mark.hip", "seqcdc_resolve.hip", "seqcdc_api.cpp", "seqcdc_autotune.cpp", "seqcdc_dedup.cpp", "seqcdc_server.cpp", "seqcdc_graph.cpp", "seqcdc_noalloc.hip", "seqcdc_fingerprint.hip", "seqcdc_calibrate.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
          # no packed FP32 instructions in any kernel

@@ -227,9 +227,11 @@ int plan_init(Plan* pl, int device) {
 
 void plan_free(Plan* pl) {
   if (pl->pending) (void)hipEventSynchronize(pl->call_done);
-  for (DevBuf* b : {&pl->eo, &pl->esum, &pl->list, &pl->cont, &pl->chains, &pl->tables, &pl->flags, &pl->misc}) b->release();
+  for (DevBuf* b : {&pl->eo, &pl->esum, &pl->list, &pl->cont, &pl->chains, &pl->tables, &pl->flags, &pl->misc, &pl->aux})
+    b->release();
   pl->staging.release();
   pl->readback.release();
+  pl->aux_host.release();
   for (hipEvent_t& e : pl->tev)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t& e : pl->ev_mark)

@@ -58,7 +58,8 @@ struct Plan {
   std::string arch;
   std::mutex mu;
   DevBuf eo, esum, list, cont, chains, tables, flags, misc;
-  HostBuf staging, readback;
+  DevBuf aux;        // calibration: candidates' cut lists and statistics
+  HostBuf staging, readback, aux_host;
   hipEvent_t call_done = nullptr, upload_done = nullptr;
   bool pending = false, upload_pending = false;
   // the last tables uploaded, and the device buffer (address, capacity) they
