@@ -46,11 +46,13 @@ extern "C" {
 
 #define SEQCDC_INCREASING 0u /* Sec. III-A "Modes of operation" */
 #define SEQCDC_DECREASING 1u
+#define SEQCDC_SIGNED 2u /* mode flag: compare bytes as signed (two's complement) values, as the 8-bit signed
+                            vector compares of Sec. III-D would; the default reading is unsigned */
 #define SEQCDC_NO_SKIP 0xFFFFFFFFu /* skip_trigger value that disables content-based skipping */
 
 /* SeqCDC parameters (Sec. III; Table I; min/max rule of Sec. VI). */
 typedef struct {
-  uint32_t mode;         /* SEQCDC_INCREASING or SEQCDC_DECREASING */
+  uint32_t mode;         /* SEQCDC_INCREASING or SEQCDC_DECREASING, optionally | SEQCDC_SIGNED */
   uint32_t seq_length;   /* bytes in the monotone run, 2..16 */
   uint64_t min_size;     /* >= seq_length */
   uint64_t max_size;     /* >= min_size, <= 1 GiB */

@@ -22,6 +22,7 @@ _lib = None
 
 INCREASING = 0
 DECREASING = 1
+SIGNED = 2  # mode flag: compare bytes as signed values
 NO_SKIP = 0xFFFFFFFF
 
 

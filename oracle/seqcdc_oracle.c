@@ -27,6 +27,9 @@
  *    that limit also ends the chunk there.
  *  - skip_trigger >= 0xFFFFFFFF disables skipping (the paper's BASE
  *    ablation, Sec. VI-C).
+ *  - Variant: with the ORACLE_SIGNED flag in `mode`, bytes are compared as
+ *    signed (two's complement) values, as 8-bit signed vector compares would
+ *    compare them (Sec. III-D's intrinsics); the reading above is unsigned.
  * Parity is pinned by hand-worked byte strings, closed forms, a mode
  * symmetry, brute force against a separately written bitmap-level
  * definition, invariants and exact expectations on random bytes.
@@ -35,15 +38,21 @@
 
 #define ORACLE_INCREASING 0u
 #define ORACLE_DECREASING 1u
+#define ORACLE_SIGNED 2u /* flag: bytes are signed values */
+
+/* A byte's value under the mode: 0..255, or -128..127 with ORACLE_SIGNED. */
+static int value(unsigned mode, uint8_t x) { return (mode & ORACLE_SIGNED) ? (int)(int8_t)x : (int)x; }
 
 /* Target order (Sec. III-A "Modes of operation"): in Increasing mode a pair
  * (x, y) of neighbouring bytes is favourable when y > x and opposing when
  * y < x; Decreasing mode swaps the two. */
 static int favourable(unsigned mode, uint8_t x, uint8_t y) {
-  return mode == ORACLE_INCREASING ? (y > x) : (y < x);
+  const int vx = value(mode, x), vy = value(mode, y);
+  return (mode & ORACLE_DECREASING) == 0 ? (vy > vx) : (vy < vx);
 }
 static int opposing(unsigned mode, uint8_t x, uint8_t y) {
-  return mode == ORACLE_INCREASING ? (y < x) : (y > x);
+  const int vx = value(mode, x), vy = value(mode, y);
+  return (mode & ORACLE_DECREASING) == 0 ? (vy < vx) : (vy > vx);
 }
 
 /*
@@ -53,7 +62,7 @@ static int opposing(unsigned mode, uint8_t x, uint8_t y) {
  */
 int64_t oracle_chunk(const uint8_t *b, uint64_t n, unsigned mode, unsigned seq_length, uint64_t min_size,
                      uint64_t max_size, uint64_t skip_trigger, uint64_t skip_size, uint64_t *cuts, uint64_t cap) {
-  if (mode > 1 || seq_length < 2 || min_size < seq_length || max_size < min_size || skip_trigger < 1) return -1;
+  if (mode > 3 || seq_length < 2 || min_size < seq_length || max_size < min_size || skip_trigger < 1) return -1;
   int skipping = skip_trigger < 0xFFFFFFFFull;
   uint64_t count = 0;
   uint64_t c = 0; /* start of the current chunk */
@@ -111,7 +120,7 @@ int64_t oracle_chunk(const uint8_t *b, uint64_t n, unsigned mode, unsigned seq_l
  * words = ceil(n / 64); bits at q >= n are zero.
  */
 int oracle_mark(const uint8_t *b, uint64_t n, unsigned mode, unsigned seq_length, uint64_t *E, uint64_t *O) {
-  if (mode > 1 || seq_length < 2) return -1;
+  if (mode > 3 || seq_length < 2) return -1;
   uint64_t words = (n + 63) / 64;
   for (uint64_t w = 0; w < words; w++) E[w] = O[w] = 0;
   for (uint64_t q = 1; q < n; q++)

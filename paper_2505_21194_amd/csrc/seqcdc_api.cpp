@@ -45,7 +45,7 @@ int hip_fail(hipError_t e, const char* what) {
 
 int validate(const seqcdc_params* p) {
   if (!p) return fail(SEQCDC_EINVAL, "params is NULL");
-  if (p->mode > 1) return fail(SEQCDC_EINVAL, "mode must be 0 (increasing) or 1 (decreasing)");
+  if (p->mode > 3) return fail(SEQCDC_EINVAL, "mode must be 0 (increasing) or 1 (decreasing), optionally | 2 (signed)");
   if (p->seq_length < 2 || p->seq_length > 16) return fail(SEQCDC_EINVAL, "seq_length must be in [2, 16]");
   if (p->min_size < p->seq_length) return fail(SEQCDC_EINVAL, "min_size must be >= seq_length");
   if (p->max_size < p->min_size) return fail(SEQCDC_EINVAL, "max_size must be >= min_size");

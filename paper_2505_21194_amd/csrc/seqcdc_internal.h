@@ -25,7 +25,7 @@ struct FileDesc {
   u64 n;                // length in bytes
   u32* eo;              // 4 * ceil(n/64) dwords of mark bits
   uint8_t* esum;        // ceil(n/1024) bytes (+ padding to 16): block holds a run end
-  u32 mode;             // 0 increasing, 1 decreasing
+  u32 mode;             // bit 0: decreasing; bit 1: bytes compared as signed values
   u32 sl;               // SeqLength (bytes in the run), 2..16
   u64 min_size, max_size;
   u32 trig;             // SkipTrigger, kNoSkip = off

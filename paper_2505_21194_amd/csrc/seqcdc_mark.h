@@ -146,7 +146,9 @@ __device__ __forceinline__ void mark_span(const FileDesc& F, u64 span, u32 span_
   const u32 lane = lane_id();
   const uint8_t* data = F.data;
   const u64 n = F.n;
-  const u32 down_is_fav = F.mode;  // decreasing mode: favourable = byte below its predecessor
+  const u32 down_is_fav = F.mode & 1;  // decreasing mode: favourable = byte below its predecessor
+  // signed bytes: x ^ 0x80 orders as the signed value of x, so the unsigned compares then compare signed values
+  const u32 flip = (F.mode & 2) ? 0x80808080u : 0u;
   const u32 runlen = F.sl - 1;
   SEQCDC_GLOBAL u32* __restrict__ eo = as_global(F.eo);
   SEQCDC_GLOBAL uint8_t* __restrict__ esum = as_global(F.esum);
@@ -158,6 +160,8 @@ __device__ __forceinline__ void mark_span(const FileDesc& F, u64 span, u32 span_
   if (blk > 0 && blk < blk_end) {
     u32 h[4];
     load_halo(data, n, blk * kMarkBlock, h);
+#pragma unroll
+    for (int k = 0; k < 4; k++) h[k] ^= flip;
     u32 up, dn;
     compare16(h, 0u, up, dn);  // bit 0 is wrong (unknown predecessor) but is never used for SeqLength <= 16
     carry_fav = down_is_fav ? dn : up;
@@ -177,6 +181,8 @@ __device__ __forceinline__ void mark_span(const FileDesc& F, u64 span, u32 span_
       const u64 B = (blk + d) * kMarkBlock;
       u32 x[4];
       block_bytes(data, ld[d], x);
+#pragma unroll
+      for (int k = 0; k < 4; k++) x[k] ^= flip;
       const u32 last = x[3] >> 24;
       const u32 prev = shift_up_lanes(last, carry_byte);
       u32 up, dn;

@@ -274,6 +274,7 @@ struct DirectChain {
   u32 nwin;             // ceil(n / 1024)
   u32 r;                // first byte's offset in its chunk (0..15)
   u32 down_is_fav;      // decreasing mode
+  u32 flip;             // 0x80808080 for signed bytes (x ^ 0x80 orders as the signed value), else 0
   u32 min_size, max_size, sl, trig, skip;
   u32 cur;              // window whose bits are held (kNone = none)
   u32 cur_slot;         // its slot
@@ -291,7 +292,8 @@ __device__ __forceinline__ void chain_init(DirectChain& ch, const FileDesc& F, S
   ch.n = F.n;
   ch.last_chunk = F.n ? (ch.r + F.n - 1) >> 4 : 0;
   ch.nwin = (u32)((F.n + kDirectWin - 1) / kDirectWin);
-  ch.down_is_fav = F.mode;
+  ch.down_is_fav = F.mode & 1;
+  ch.flip = (F.mode & 2) ? 0x80808080u : 0u;
   ch.min_size = (u32)F.min_size;
   ch.max_size = (u32)F.max_size;
   ch.sl = F.sl;
@@ -373,8 +375,8 @@ __device__ __forceinline__ void ensure(DirectChain& ch, u32 w, u32 hint) {
   u32 halo[4], x[4];
 #pragma unroll
   for (int k = 0; k < 4; k++) {
-    halo[k] = __builtin_amdgcn_alignbyte(dw[k + 1], dw[k], sh);
-    x[k] = __builtin_amdgcn_alignbyte(dw[k + 5], dw[k + 4], sh);
+    halo[k] = __builtin_amdgcn_alignbyte(dw[k + 1], dw[k], sh) ^ ch.flip;
+    x[k] = __builtin_amdgcn_alignbyte(dw[k + 5], dw[k + 4], sh) ^ ch.flip;
   }
   // the next fetches go to other slots while the bits are computed
   prefetch_raw(ch, w + 1, w);

@@ -12,7 +12,9 @@ NO_SKIP = 0xFFFFFFFF
 
 def facts(b, mode, seq_length):
     n = len(b)
-    if mode == 0:
+    if mode & 2:  # signed bytes: two's complement values -128..127
+        b = [x - 256 if x >= 128 else x for x in b]
+    if mode & 1 == 0:
         fav = [False] + [b[i] > b[i - 1] for i in range(1, n)]
         opp = [False] + [b[i] < b[i - 1] for i in range(1, n)]
     else:

@@ -47,7 +47,7 @@ def test_validation(seq):
     ok = seq.make_params()
     assert seq.seqcdc_params_validate(ok) == 0
     bad = [dict(seq_length=1), dict(seq_length=17), dict(min_size=3, seq_length=5), dict(min_size=100, max_size=50),
-           dict(skip_trigger=0), dict(mode=2)]
+           dict(skip_trigger=0), dict(mode=4)]
     for b in bad:
         p = dict(mode=0, seq_length=5, min_size=4096, max_size=16384, skip_trigger=50, skip_size=256)
         p.update(b)

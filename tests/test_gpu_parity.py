@@ -90,7 +90,7 @@ def test_mark_bitmaps(env, n):
     low = (synth.uniform(n, seed=n + 1) % 4).astype(np.uint8)  # many equal pairs and short runs
     for d, tag in ((data, "uniform"), (low, "alphabet4")):
         for sl in (2, 3, 5, 6, 9, 16):
-            for mode in (0, 1):
+            for mode in (0, 1, 2, 3):  # increasing / decreasing, unsigned / signed bytes
                 for off in ((0, 5) if n < 5000 else (0, 13)):
                     _say("mark", tag, n, sl, mode, off)
                     t, keep = _dev(torch, d, off)
@@ -117,6 +117,17 @@ def test_mixed_32mib(env, avg, mode, sl):
     kb = 1024
     trig, skip = (50, 256) if avg == 8 else (50, 512)
     _check(env, data, P(mode=mode, sl=sl, mn=avg * kb // 2, mx=2 * avg * kb, trig=trig, skip=skip), label="mixed")
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+@pytest.mark.parametrize("offset", [0, 5])
+def test_signed_bytes(env, mode, offset):
+    """The signed-byte variant (bytes compared as two's complement values), both resolve modes, several parameter
+    sets, aligned and misaligned input."""
+    data = synth.mixed(8 << 20, seed=60 + mode)
+    for params in (P(mode=mode), P(mode=mode, sl=6, mn=8192, mx=32768, skip=512), P(mode=mode, sl=3, mn=64, mx=512,
+                                                                                    trig=5, skip=17)):
+        _check(env, data, params, offset=offset, label="signed")
 
 
 @pytest.fixture

@@ -198,7 +198,7 @@ def test_invalid_parameters_rejected():
         with pytest.raises(ValueError):
             oracle.chunk(d, **bad)
     with pytest.raises(ValueError):
-        oracle.chunk(d, mode=2, seq_length=3, min_size=3, max_size=4)
+        oracle.chunk(d, mode=4, seq_length=3, min_size=3, max_size=4)
 
 
 # ---------------------------------------------------------------- invariants
@@ -244,3 +244,44 @@ def test_resync_after_prefix_insertion(seed):
     far = a[a > (2 << 20)]
     shared = np.isin(far, b).mean()
     assert shared > 0.99
+
+
+# ---------------------------------------------------------------- signed-byte variant
+def test_signed_hand_worked():
+    """Bytes 0x7E 0x7F 0x80 0x81 increase as unsigned values but fall from 127 to -128 as signed ones (the 8-bit
+    signed compares of Sec. III-D's intrinsics): with SeqLength 4 the unsigned reading cuts after the run, the
+    signed one finds none and cuts at the maximum; SeqLength 2 finds the signed runs 0x7E 0x7F and 0x80 0x81, and
+    the equal bytes after them end at the stream end."""
+    b = np.array([0x7E, 0x7F, 0x80, 0x81, 0x00, 0x00, 0x00, 0x00], np.uint8)
+    kw = dict(min_size=4, max_size=6, skip_trigger=oracle.NO_SKIP, skip_size=0)
+    assert oracle.chunk(b, mode=0, seq_length=4, **kw).tolist() == [4, 8]
+    assert oracle.chunk(b, mode=oracle.SIGNED, seq_length=4, **kw).tolist() == [6, 8]
+    assert oracle.chunk(b, mode=oracle.SIGNED, seq_length=2, min_size=2, max_size=6, skip_trigger=oracle.NO_SKIP,
+                        skip_size=0).tolist() == [2, 4, 8]
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_signed_is_unsigned_of_flipped_bytes(mode):
+    """x < y as signed bytes exactly when (x ^ 0x80) < (y ^ 0x80) as unsigned ones (two's complement), so the signed
+    variant must equal the unsigned one on the bytes with their top bit flipped."""
+    data = synth.mixed(2 << 20, seed=70 + mode)
+    for p in (dict(seq_length=5, min_size=4096, max_size=16384, skip_trigger=50, skip_size=256),
+              dict(seq_length=3, min_size=64, max_size=1024, skip_trigger=7, skip_size=33)):
+        a = oracle.chunk(data, mode=mode | oracle.SIGNED, **p)
+        b = oracle.chunk(data ^ np.uint8(0x80), mode=mode, **p)
+        assert np.array_equal(a, b)
+    E1, O1 = oracle.mark(data, mode | oracle.SIGNED, 5)
+    E2, O2 = oracle.mark(data ^ np.uint8(0x80), mode, 5)
+    assert np.array_equal(E1, E2) and np.array_equal(O1, O2)
+
+
+def test_signed_brute_force_around_the_sign_change():
+    """All strings over {126, 127, 128, 129} up to length 7, against the definition-level reference reading the
+    bytes as two's complement values."""
+    for n in range(0, 8):
+        for s in itertools.product((126, 127, 128, 129), repeat=n):
+            b = np.array(s, np.uint8)
+            for mode in (2, 3):
+                for sl, mn, mx, trig, skip in ((2, 2, 5, 1, 0), (3, 3, 6, 2, 1), (3, 4, 7, defref.NO_SKIP, 0)):
+                    kw = dict(mode=mode, seq_length=sl, min_size=mn, max_size=mx, skip_trigger=trig, skip_size=skip)
+                    assert oracle.chunk(b, **kw).tolist() == defref.chunk(b, **kw), (s, kw)
