@@ -32,6 +32,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
 METRIC = "chunking GB/s on 1 MI355X (batched vs plain) + % HBM peak; p99 request latency"
+RUN7 = np.array([10, 20, 30, 40, 50, 5, 3], np.uint8)  # a 7-byte pattern holding a run of 5 increasing bytes
 PROBE_STEPS = 6  # chunking steps of a whole-step traffic probe (each launches the step's kernels once)
 STEP_TRAFFIC = {"plain": os.path.join(HERE, "profiles", "step_traffic_plain1GiB.json"),
                 "batched": os.path.join(HERE, "profiles", "step_traffic_batched4096.json"),
@@ -347,6 +348,12 @@ def sweep(seq, torch, stream, d, steps, tune):
     p6.seq_length = 6
     cases.append(("1 GiB mixed, increasing, avg 8 KiB parameters with SeqLength 6", d, p6))
     cases.append(("8 MiB uniform (seed 0), increasing, avg 8 KiB, max 16 KiB", small, seq.seqcdc_params_for_avg(8192)))
+    # the worst case for speculation: a 7-byte pattern holding an increasing run of 5, repeated: every chunk ends
+    # just past a run at the same phase of the pattern, chunk lengths (4096 or 4101 bytes) do not divide the segment
+    # length, and chains from different starts never meet, so the exact path is one sequential walk
+    p7 = torch.from_numpy(np.resize(RUN7, d.numel())).to(d.device)
+    cases.append(("1 GiB periodic 7-byte pattern with a run (never resynchronises), increasing, avg 8 KiB", p7,
+                  seq.seqcdc_params_for_avg(8192)))
     p64 = seq.seqcdc_params_for_avg(8192)
     p64.max_size = 65536
     cases.append(("8 MiB uniform (seed 0), increasing, avg 8 KiB, max 64 KiB", small, p64))
@@ -356,19 +363,23 @@ def sweep(seq, torch, stream, d, steps, tune):
             n = t.numel()
             cap = seq.seqcdc_max_cuts(n, p)
             cuts = torch.empty(cap, dtype=torch.int64, device=t.device)
-            if tune and n >= (64 << 20):
+            worst = "periodic" in name
+            if tune and n >= (64 << 20) and not worst:
                 seq.seqcdc_autotune(plan, t.data_ptr(), n, p, stream=stream)
-            for _ in range(2):
+            reps = 2 if worst else steps  # the sequential walk takes a few hundred ms
+            for _ in range(1 if worst else 2):
                 cnt = seq.seqcdc_chunk(t.data_ptr(), n, p, cuts.data_ptr(), cap, stream=stream, plan=plan)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            for _ in range(steps):
+            for _ in range(reps):
                 cnt = seq.seqcdc_chunk(t.data_ptr(), n, p, cuts.data_ptr(), cap, stream=stream, plan=plan)
             torch.cuda.synchronize()
-            dt = (time.perf_counter() - t0) / steps
+            dt = (time.perf_counter() - t0) / reps
             seg, span, waves = seq.seqcdc_plan_get_tuning(plan, n, p)
             out.append({"workload": name, "ms": round(dt * 1e3, 4), "GBps": round(n / dt / 1e9, 1), "cuts": cnt,
                         "tuning": {"segment_bytes": seg, "mark_span_blocks": span, "waves_per_cu": waves}})
+            if "periodic" in name:  # its cuts, for the oracle check made after every measurement
+                out[-1]["_check"] = (cuts[:cnt].cpu().numpy().astype(np.uint64), p)
             del cuts
     finally:
         seq.seqcdc_plan_destroy(plan)
@@ -503,6 +514,12 @@ def serving_parity(checks):
         got = checks["got"].get(i)
         ok = ok and got is not None and got.size == want.size and bool(np.array_equal(got, want))
     return ok
+
+
+def oracle_chunk(data, p):
+    import oracle
+    return oracle.chunk(data, mode=p.mode, seq_length=p.seq_length, min_size=p.min_size, max_size=p.max_size,
+                        skip_trigger=p.skip_trigger, skip_size=p.skip_size)
 
 
 def cpu_baseline(host, p, seconds):
@@ -652,7 +669,7 @@ def main():
         log("calibration: %s" % extra["calibration"])
     if not args.no_sweep:  # last: its autotuning sets the process-wide choices of more parameter classes
         extra["sweep"] = sweep(seq, torch, stream, d, args.steps, not args.no_tune)
-        log("sweep: %s" % extra["sweep"])
+        log("sweep: %s" % [{k: v for k, v in c.items() if k != "_check"} for c in extra["sweep"]])
 
     cpu = None
     if not args.no_cpu:
@@ -666,6 +683,13 @@ def main():
         if "serving" in extra:
             extra["serving"]["parity_vs_oracle"] = serving_parity(extra["serving"]["_checks"])
             log("serving parity %s" % extra["serving"]["parity_vs_oracle"])
+        for case in extra.get("sweep", []):
+            if "_check" in case:
+                got, pp = case.pop("_check")
+                host7 = np.resize(RUN7, n)
+                want = oracle_chunk(host7, pp)
+                case["parity_vs_oracle"] = bool(got.size == want.size and np.array_equal(got, want))
+                log("%s: parity %s" % (case["workload"], case["parity_vs_oracle"]))
         if "dedup" in extra:
             extra["dedup"]["parity_vs_oracle"] = dedup_parity(extra["dedup"]["_check"], extra["dedup"]["orig_bytes"],
                                                               extra["dedup"]["unique_bytes"])

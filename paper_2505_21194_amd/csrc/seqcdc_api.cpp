@@ -227,7 +227,8 @@ int plan_init(Plan* pl, int device) {
 
 void plan_free(Plan* pl) {
   if (pl->pending) (void)hipEventSynchronize(pl->call_done);
-  for (DevBuf* b : {&pl->eo, &pl->esum, &pl->list, &pl->cont, &pl->chains, &pl->tables, &pl->flags, &pl->misc, &pl->aux})
+  for (DevBuf* b : {&pl->eo, &pl->esum, &pl->list, &pl->cont, &pl->chains, &pl->tables, &pl->flags, &pl->misc, &pl->aux,
+                    &pl->ovf})
     b->release();
   pl->staging.release();
   pl->readback.release();
@@ -280,6 +281,27 @@ static int ensure_side(Plan* pl) {
   return SEQCDC_OK;
 }
 
+// Bytes of the per-chain workspace carved by carve_chain_ws.
+static size_t chain_ws_bytes(u64 nchains) {
+  return carve_size({nchains * 4, nchains * 8, nchains * 4, nchains * 4, nchains * 8, nchains * 4, nchains * 4,
+                     nchains * 8, nchains * 8, nchains * 8, nchains * 8});
+}
+
+// The per-chain workspace fields of ws, carved from `cur` (chain_ws_bytes of them).
+static void carve_chain_ws(ChainWs& ws, char* cur, u64 nchains) {
+  ws.list_cnt = carve<u32>(cur, nchains);
+  ws.conv_val = carve<u64>(cur, nchains);
+  ws.conv_chain = carve<u32>(cur, nchains);
+  ws.conv_idx = carve<i32>(cur, nchains);
+  ws.cont_cnt = carve<u64>(cur, nchains);
+  ws.active = carve<u32>(cur, nchains);
+  ws.entry_idx = carve<i32>(cur, nchains);
+  ws.jumps = (u32*)carve<u64>(cur, nchains);
+  ws.out_off = carve<u64>(cur, nchains);
+  ws.covered = (u32*)carve<u64>(cur, nchains);
+  ws.ovf_start = carve<u64>(cur, nchains);
+}
+
 // Continuation buffer entries per chain for segments of seg bytes.
 static u32 cont_cap_for(u64 seg, u64 min_size) {
   return (u32)std::max<u64>(1024, std::min<u64>(2 * seg / min_size + 64, 4096));
@@ -312,22 +334,21 @@ int plan_reserve(Plan* pl, u64 bytes, u32 nfiles, const seqcdc_params* params, u
       nfiles + std::min<u64>(std::max<u64>(bytes / seg_min, (u64)pl->cus * waves), bytes / (64 * 1024)) + 1;
   const u64 spans = bytes / ((u64)span_min * kMarkBlock) + nfiles;
   const u64 nhint = spans / kHintSpans + 2;
-  const size_t chain_bytes = carve_size({nchains * 4, nchains * 8, nchains * 4, nchains * 4, nchains * 4, nchains * 4,
-                                         nchains * 4, nchains * 4, nchains * 8, nchains * 4, nchains * 8});
+  const size_t chain_bytes = chain_ws_bytes(nchains);
   const size_t table_bytes = carve_size({nfiles * sizeof(FileDesc), nchains * 4, nchains * 8, nchains * 8,
                                          nchains * 4, nchains * 4 + 4, nfiles * 4ull + 4, nchains * 4 + 4, nhint * 4});
-  const size_t sizes[8] = {bytes / 4 + 16ull * nfiles + 512, bytes / 1024 + 32ull * nfiles + 256,
+  const size_t sizes[9] = {bytes / 4 + 16ull * nfiles + 512, bytes / 1024 + 32ull * nfiles + 256,
                            (bytes / min_min + 2 * nchains) * 8, nchains * cont_cap * 8, chain_bytes, table_bytes,
-                           16 * (kMaxGroups + 2) * 4, table_bytes};
-  DevBuf* bufs[7] = {&pl->eo, &pl->esum, &pl->list, &pl->cont, &pl->chains, &pl->tables, &pl->flags};
+                           16 * (kMaxGroups + 2) * 4, (bytes / min_min + 2 * nfiles) * 8, table_bytes};
+  DevBuf* bufs[8] = {&pl->eo, &pl->esum, &pl->list, &pl->cont, &pl->chains, &pl->tables, &pl->flags, &pl->ovf};
   u64 sum = 0;
-  for (size_t i = 0; i < 8; i++) sum += std::max<size_t>(sizes[i] + sizes[i] / 4, 4096);  // as reserve() rounds
+  for (size_t i = 0; i < 9; i++) sum += std::max<size_t>(sizes[i] + sizes[i] / 4, 4096);  // as reserve() rounds
   if (total) *total = sum;
   if (dry) return SEQCDC_OK;
   int rc;
-  for (int i = 0; i < 7; i++)
+  for (int i = 0; i < 8; i++)
     if ((rc = bufs[i]->reserve(sizes[i]))) return rc;
-  if ((rc = pl->staging.reserve(sizes[7]))) return rc;
+  if ((rc = pl->staging.reserve(sizes[8]))) return rc;
   return SEQCDC_OK;
 }
 
@@ -353,7 +374,7 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   for (u32 f = 0; f < nfiles; f++) perm[f] = f;
   if (G > 1) std::stable_sort(perm.begin(), perm.end(), [&](u32 a, u32 b) { return specs[a].n > specs[b].n; });
   std::vector<FileDesc> fd(nfiles);
-  u64 eo_bytes = 0, esum_bytes = 0, spans = 0, list_entries = 0, cont_entries = 0;
+  u64 eo_bytes = 0, esum_bytes = 0, spans = 0, list_entries = 0, cont_entries = 0, ovf_entries = 0;
   u32 nchains = 0, cont_cap = 64;
   const u32 U = pl->span_blocks_for(specs[0].p);
   const u32 waves = pl->waves_for(specs[0].p);
@@ -383,9 +404,12 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
     d.out = s.out;
     d.out_cap = s.out_cap;
     d.out_count = s.out_count;
+    d.ovf0 = 0;
     if (d.nseg > 1) {
       multi.push_back(f);
       cont_cap = std::max<u32>(cont_cap, cont_cap_for(d.seg, d.min_size));
+      d.ovf0 = ovf_entries;
+      ovf_entries += d.n / d.min_size + 2;
     }
   }
   if (mark_only) {
@@ -454,10 +478,8 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
   if ((rc = pl->esum.reserve(direct ? 256 : esum_bytes + 256))) return rc;
   if ((rc = pl->list.reserve(std::max<u64>(list_entries, 1) * 8))) return rc;
   if ((rc = pl->cont.reserve(std::max<u64>(cont_entries, 1) * 8))) return rc;
-  const size_t chain_bytes = carve_size({nchains * 4ull, nchains * 8ull, nchains * 4ull, nchains * 4ull,
-                                         nchains * 4ull, nchains * 4ull, nchains * 4ull, nchains * 4ull,
-                                         nchains * 8ull, nchains * 4ull, nchains * 8ull});
-  if ((rc = pl->chains.reserve(chain_bytes))) return rc;
+  if ((rc = pl->chains.reserve(chain_ws_bytes(nchains)))) return rc;
+  if ((rc = pl->ovf.reserve(std::max<u64>(ovf_entries, 1) * 8))) return rc;
   const u64 nhint = spans / kHintSpans + 2;
   const size_t table_bytes =
       carve_size({nfiles * sizeof(FileDesc), nchains * 4ull, nchains * 8ull, nchains * 8ull, nchains * 4ull,
@@ -533,23 +555,14 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
 
   // ---- chain workspace
   ChainWs ws;
-  char* cc = (char*)pl->chains.p;
   ws.chain_file = (u32*)dev(h_chain_file);
   ws.list = (u64*)pl->list.p;
   ws.list_off = (u64*)dev(h_list_off);
   ws.cont = (u64*)pl->cont.p;
   ws.cont_off = (u64*)dev(h_cont_off);
   ws.cont_cap = cont_cap;
-  ws.list_cnt = carve<u32>(cc, nchains);
-  ws.conv_val = carve<u64>(cc, nchains);
-  ws.conv_chain = carve<u32>(cc, nchains);
-  ws.conv_idx = carve<i32>(cc, nchains);
-  ws.cont_cnt = carve<u32>(cc, nchains);
-  ws.active = carve<u32>(cc, nchains);
-  ws.entry_idx = carve<i32>(cc, nchains);
-  ws.jumps = (u32*)carve<u64>(cc, nchains);
-  ws.out_off = carve<u64>(cc, nchains);
-  ws.covered = (u32*)carve<u64>(cc, nchains);
+  ws.ovf = (u64*)pl->ovf.p;
+  carve_chain_ws(ws, (char*)pl->chains.p, nchains);
 
   // ---- launches
   u32* heads = (u32*)pl->flags.p;  // [0] pass A head, [16] pass B head
@@ -569,8 +582,8 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
       HIP_TRY(launch_continue(d_files, ws, (const u32*)dev(h_border), nb, heads + 16,
                               std::max<u32>(1, std::min<u32>(groups, (nb + 3) / 4)), direct, st));
       HIP_TRY(timing_mark(pl, 3, st));
-      HIP_TRY(launch_stitch(d_files, ws, (const u32*)dev(h_multi), (u32)multi.size(), st));
-      HIP_TRY(launch_compact(d_files, ws, (const u32*)dev(h_compact), (u32)compact.size(), direct, st));
+      HIP_TRY(launch_stitch(d_files, ws, (const u32*)dev(h_multi), (u32)multi.size(), direct, st));
+      HIP_TRY(launch_compact(d_files, ws, (const u32*)dev(h_compact), (u32)compact.size(), st));
     } else {
       HIP_TRY(timing_mark(pl, 3, st));
     }
@@ -613,8 +626,8 @@ int run_batch(Plan* pl, const Spec* specs, u32 nfiles, hipStream_t st, bool mark
       HIP_TRY(launch_continue(d_files, ws, d_border + border_first, nb - border_first, heads + 16 * (G + 1),
                               std::max<u32>(1, std::min<u32>(groups, (nb - border_first + 3) / 4)), false, sb));
       HIP_TRY(timing_mark(pl, 3, sb));
-      HIP_TRY(launch_stitch(d_files, ws, (const u32*)dev(h_multi), (u32)multi.size(), sb));
-      HIP_TRY(launch_compact(d_files, ws, (const u32*)dev(h_compact), (u32)compact.size(), false, sb));
+      HIP_TRY(launch_stitch(d_files, ws, (const u32*)dev(h_multi), (u32)multi.size(), false, sb));
+      HIP_TRY(launch_compact(d_files, ws, (const u32*)dev(h_compact), (u32)compact.size(), sb));
     } else {
       HIP_TRY(hipStreamWaitEvent(sb, pl->ev_chain_last, 0));
       HIP_TRY(timing_mark(pl, 3, sb));

@@ -37,6 +37,7 @@ struct FileDesc {
   u64* out;             // final cut list destination
   u64 out_cap;          // entries available at out
   u64* out_count;       // where the final count is written (device)
+  u64 ovf0;             // multi-segment files: first entry of the file's overflow region (n/min_size + 2 entries)
 };
 
 }  // namespace seqcdc

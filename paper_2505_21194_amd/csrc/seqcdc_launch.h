@@ -17,9 +17,9 @@ hipError_t launch_chains(const FileDesc* d_files, const ChainWs& ws, const u32* 
                          u32 groups, bool direct, hipStream_t st);
 hipError_t launch_continue(const FileDesc* d_files, const ChainWs& ws, const u32* d_order, u32 nitems, u32* head,
                            u32 groups, bool direct, hipStream_t st);
-hipError_t launch_stitch(const FileDesc* d_files, const ChainWs& ws, const u32* d_multi, u32 nmulti,
+hipError_t launch_stitch(const FileDesc* d_files, const ChainWs& ws, const u32* d_multi, u32 nmulti, bool direct,
                          hipStream_t st);
-hipError_t launch_compact(const FileDesc* d_files, const ChainWs& ws, const u32* d_chains, u32 nchains, bool direct,
+hipError_t launch_compact(const FileDesc* d_files, const ChainWs& ws, const u32* d_chains, u32 nchains,
                           hipStream_t st);
 
 }  // namespace seqcdc

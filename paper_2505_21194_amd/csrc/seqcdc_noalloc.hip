@@ -132,7 +132,9 @@ extern "C" int seqcdc_chunk_noalloc(const void* d_stream, uint64_t n, const seqc
   const u64 o_conv_val = cv.take(nseg * 8ull);
   const u64 o_conv_chain = cv.take(nseg * 4ull);
   const u64 o_conv_idx = cv.take(nseg * 4ull);
-  const u64 o_cont_cnt = cv.take(nseg * 4ull);
+  const u64 o_cont_cnt = cv.take(nseg * 8ull);
+  const u64 o_ovf_start = cv.take(nseg * 8ull);
+  const u64 o_ovf = cv.take(multi ? (n / p->min_size + 2) * 8 : 8);
   const u64 o_active = cv.take(nseg * 4ull);
   const u64 o_entry_idx = cv.take(nseg * 4ull);
   const u64 o_jumps = cv.take(nseg * 8ull);
@@ -170,6 +172,7 @@ extern "C" int seqcdc_chunk_noalloc(const void* d_stream, uint64_t n, const seqc
   fd.out = d_cuts;
   fd.out_cap = cap;
   fd.out_count = d_count;
+  fd.ovf0 = 0;
 
   const FileDesc* d_files = (const FileDesc*)(base + o_files);
   u32* heads = (u32*)(base + o_heads);
@@ -189,7 +192,9 @@ extern "C" int seqcdc_chunk_noalloc(const void* d_stream, uint64_t n, const seqc
   ws.conv_val = (u64*)(base + o_conv_val);
   ws.conv_chain = (u32*)(base + o_conv_chain);
   ws.conv_idx = (i32*)(base + o_conv_idx);
-  ws.cont_cnt = (u32*)(base + o_cont_cnt);
+  ws.cont_cnt = (u64*)(base + o_cont_cnt);
+  ws.ovf_start = (u64*)(base + o_ovf_start);
+  ws.ovf = (u64*)(base + o_ovf);
   ws.cont = (u64*)(base + o_cont);
   ws.cont_off = (u64*)(base + o_cont_off);
   ws.cont_cap = cont_cap;
@@ -211,9 +216,9 @@ extern "C" int seqcdc_chunk_noalloc(const void* d_stream, uint64_t n, const seqc
     if ((e = launch_continue(d_files, ws, iota, nb, heads + 16, std::max<u32>(1, std::min<u32>(groups, (nb + 3) / 4)),
                              false, st)) != hipSuccess)
       return hip_fail(e, "continue kernel");
-    if ((e = launch_stitch(d_files, ws, (const u32*)(base + o_multi), 1, st)) != hipSuccess)
+    if ((e = launch_stitch(d_files, ws, (const u32*)(base + o_multi), 1, false, st)) != hipSuccess)
       return hip_fail(e, "stitch kernel");
-    if ((e = launch_compact(d_files, ws, iota, nseg, false, st)) != hipSuccess) return hip_fail(e, "compact kernel");
+    if ((e = launch_compact(d_files, ws, iota, nseg, st)) != hipSuccess) return hip_fail(e, "compact kernel");
   }
   return SEQCDC_OK;
 }

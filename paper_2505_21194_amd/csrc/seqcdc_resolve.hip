@@ -599,28 +599,30 @@ __device__ __forceinline__ i32 cursor_find(ListCursor& lc, u64 x) {
   }
 }
 
-// Pass B of `chain` (not the last of its file): its cuts from x on, cc of
-// them already stored, until one is also a cut of the chain that owns that
-// position (or that chain's segment start).  Starts at the exit cut with
-// cc = 0.
+constexpr u32 kOpen = 0xFFFFFFFFu;  // conv_chain of a continuation that stopped with its buffer full
+
+// A continuation of `chain` (not the last of its file) from cut x, cc of its
+// cuts already recorded: its cuts until one is also a cut of the chain that
+// owns that position (or that chain's segment start), or the stream end.  Cut
+// number i is stored at dst[i - base].  When cc reaches `stop` (pass B: the
+// continuation's buffer is full) it stops and is left open at x, the next cut
+// to examine: conv_chain = kOpen, conv_val = x.
 template <class Ch>
-__device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ files, const ChainWs& ws, u32 chain,
-                                                 SEQCDC_LOCAL u32x4* win, u64 x, u32 cc) {
-  const FileDesc& F = files[ws.chain_file[chain]];
+__device__ void walk_continuation(const FileDesc& F, const ChainWs& ws, u32 chain, SEQCDC_LOCAL u32x4* win, u64 x,
+                                  u64 cc, SEQCDC_GLOBAL u64* dst, u64 base, u64 stop) {
   const u64 n = F.n;
   const u32 nseg = F.nseg;
   u32 conv_chain = nseg;
   i32 conv_idx = -1;
-  SEQCDC_GLOBAL u64* cont = as_global(ws.cont + ws.cont_off[chain]);
   // Entries [from, cc) wait in the lanes (entry i in lane i % 64) and are
   // stored 64 at a time: a store per cut would make every later wait for a
   // window DMA wait for that store too (one counter covers loads and stores).
   const u32 lane = lane_id();
-  u32 from = cc;
+  u64 from = cc;
   u64 buf = 0;
   auto flush = [&]() {
-    const u32 i = ((cc - 1) & ~63u) + lane;
-    if (cc > from && i >= from && i < cc && i < ws.cont_cap) cont[i] = buf;
+    const u64 i = ((cc - 1) & ~63ull) + lane;
+    if (cc > from && i >= from && i < cc) dst[i - base] = buf;
     from = cc;
   };
   if (x < n) {
@@ -646,10 +648,14 @@ __device__ __forceinline__ void run_continuation(const FileDesc* __restrict__ fi
         conv_idx = idx;
         break;
       }
+      if (cc == stop) {
+        conv_chain = kOpen;
+        break;
+      }
       const u64 nx = next_cut(ch, x);
-      if (lane == (cc & 63u)) buf = x;
+      if (lane == (u32)(cc & 63)) buf = x;
       cc++;
-      if ((cc & 63u) == 0) flush();
+      if ((cc & 63) == 0) flush();
       x = nx;
       if (x >= n) break;  // reached the end of the stream: conv_chain = nseg
       if (x >= m_end) {  // x moved into a later segment: min(x / seg, nseg - 1) > m
@@ -713,7 +719,8 @@ __global__ __launch_bounds__(256) void continue_kernel(const FileDesc* __restric
     const u32 t = wave_pop(head);
     if (t >= nitems) return;
     const u32 chain = order[t];
-    run_continuation<Ch>(files, ws, chain, mine, exit_cut(ws, chain), 0);
+    walk_continuation<Ch>(files[ws.chain_file[chain]], ws, chain, mine, exit_cut(ws, chain), 0,
+                          as_global(ws.cont + ws.cont_off[chain]), 0, ws.cont_cap);
   }
 }
 
@@ -754,9 +761,18 @@ __device__ u64 block_exclusive_scan(u64 v, u64* sh, u64& total) {
 // Stitch (one workgroup per multi-segment file): the exact cut sequence
 // starts in chain 0 and moves to chain conv_chain[k] at conv_val[k].  Chains
 // strictly between k and conv_chain[k] are covered by k's continuation and
-// contribute nothing.
+// contribute nothing.  A continuation that stopped open (its buffer full, no
+// convergence yet) covers, as far as is known, everything after it; if it is
+// on the exact path, wave 0 continues it to its convergence (or the stream
+// end), storing the further cuts in the file's overflow region, and the
+// active chains are worked out again.  So the exact path is walked once, and
+// continuations that turn out not to be on it are never taken further.
+template <class Ch>
 __global__ __launch_bounds__(kStitchThreads) void stitch_kernel(const FileDesc* __restrict__ files, ChainWs ws,
                                                                 const u32* __restrict__ multi, u32 nmulti) {
+  __shared__ u32x4 swin[WaveLds<Ch>::kChunks];  // wave 0's window slots when it continues an open chain
+  __shared__ u32 s_open;
+  __shared__ u64 s_ovf_used;
   __shared__ u64 sh[kStitchWaves];
   __shared__ u32 scov[2 * kStitchLdsRanges];
   __shared__ u32 sjk[kStitchLdsJumps], sjn[kStitchLdsJumps];  // a jump's boundary and target chain
@@ -767,13 +783,16 @@ __global__ __launch_bounds__(kStitchThreads) void stitch_kernel(const FileDesc* 
   const u32 nseg = F.nseg, c0 = F.chain0;
   uint2* jumps = (uint2*)(ws.jumps + 2 * (u64)c0);
   u32* cov = ws.covered + 2 * (u64)c0;
+  if (t == 0) s_ovf_used = 0;
 
+  for (;;) {  // rounds: once, plus once per open continuation on the exact path
   // 1. boundaries whose continuation skipped at least one whole segment,
-  // with the chain each one ends in
+  // with the chain each one ends in (an open one: the end, nseg)
   u32 base = 0;
   for (u32 j0 = 0; j0 < nseg; j0 += kStitchThreads) {
     const u32 k = j0 + t;
-    const u32 nx = k + 1 < nseg ? ws.conv_chain[c0 + k] : 0u;
+    u32 nx = k + 1 < nseg ? ws.conv_chain[c0 + k] : 0u;
+    if (nx == kOpen) nx = nseg;
     const bool jump = k + 1 < nseg && nx != k + 1;
     u64 tot;
     const u32 pos = (u32)block_exclusive_scan(jump ? 1u : 0u, sh, tot);
@@ -898,7 +917,28 @@ __global__ __launch_bounds__(kStitchThreads) void stitch_kernel(const FileDesc* 
     ws.active[c0 + j] = covered ? 0u : 1u;
     if (j == 0) ws.entry_idx[c0] = 0;
   }
+  if (t == 0) s_open = nseg;
   __syncthreads();
+  // the first open continuation on the exact path, if any
+  for (u32 k = t; k + 1 < nseg; k += kStitchThreads)
+    if (ws.active[c0 + k] && ws.conv_chain[c0 + k] == kOpen) atomicMin(&s_open, k);
+  __syncthreads();
+  const u32 ko = s_open;
+  if (ko >= nseg) break;
+  if (t < 64) {  // wave 0 continues it; its further cuts go to the file's overflow region
+    const u32 chain = c0 + ko;
+    const u64 cc = ws.cont_cnt[chain];  // = cont_cap: the buffer is full
+    const u64 at = F.ovf0 + s_ovf_used;
+    walk_continuation<Ch>(F, ws, chain, (SEQCDC_LOCAL u32x4*)swin, ws.conv_val[chain], cc, as_global(ws.ovf + at), cc,
+                          ~0ull);
+    if (t == 0) {
+      ws.ovf_start[chain] = at;
+      s_ovf_used += ws.cont_cnt[chain] - cc;
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  }  // rounds
   for (u32 k = t; k + 1 < nseg; k += kStitchThreads) {
     if (!ws.active[c0 + k]) continue;
     const u32 nx = ws.conv_chain[c0 + k];
@@ -928,12 +968,11 @@ __global__ __launch_bounds__(kStitchThreads) void stitch_kernel(const FileDesc* 
 }
 
 // Compaction: one wave per chain of a multi-segment file copies its exact
-// part; a continuation longer than its buffer is regenerated by walking on.
-template <class Ch>
+// part: the main part of its list, its continuation buffer and, for a
+// continuation the stitch took further, its overflow cuts.
 __global__ __launch_bounds__(256) void compact_kernel(const FileDesc* __restrict__ files, ChainWs ws,
                                                       const u32* __restrict__ chains, u32 nchains) {
   const u32 lane = lane_id();
-  __shared__ u32x4 win[kWavesPerGroup][WaveLds<Ch>::kChunks];
   const u32 w = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6));  // wave-uniform
   if (w >= nchains) return;
   const u32 chain = chains[w];
@@ -957,23 +996,20 @@ __global__ __launch_bounds__(256) void compact_kernel(const FileDesc* __restrict
     o += (main_cnt - i < 64) ? main_cnt - i : 64;
   }
   if (!last) {
-    const u32 cc = ws.cont_cnt[chain];
-    const u32 stored = cc < ws.cont_cap ? cc : ws.cont_cap;
+    const u64 cc = ws.cont_cnt[chain];
+    const u64 stored = cc < ws.cont_cap ? cc : ws.cont_cap;
     const u64* cont = ws.cont + ws.cont_off[chain];
-    for (u32 i = 0; i < stored; i += 64) {
-      const u32 ii = i + lane;
+    for (u64 i = 0; i < stored; i += 64) {
+      const u64 ii = i + lane;
       if (ii < stored && o + (ii - i) < cap) out[o + (ii - i)] = cont[ii];
       o += (stored - i < 64) ? stored - i : 64;
     }
-    if (cc > stored) {
-      Ch ch;
-      chain_init(ch, F, (SEQCDC_LOCAL u32x4*)win[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
-      u64 x = cont[stored - 1];
-      for (u32 i = stored; i < cc; i++) {
-        x = next_cut(ch, x);
-        if (lane == 0 && o < cap) out[o] = x;
-        o++;
-      }
+    const u64 extra = cc - stored;  // cuts the stitch added after the buffer filled
+    const u64* ovf = ws.ovf + (extra ? ws.ovf_start[chain] : 0);
+    for (u64 i = 0; i < extra; i += 64) {
+      const u64 ii = i + lane;
+      if (ii < extra && o + (ii - i) < cap) out[o + (ii - i)] = ovf[ii];
+      o += (extra - i < 64) ? extra - i : 64;
     }
   }
   if (last || ws.conv_chain[chain] == F.nseg) {
@@ -1014,20 +1050,23 @@ hipError_t launch_continue(const FileDesc* d_files, const ChainWs& ws, const u32
   return hipGetLastError();
 }
 
-hipError_t launch_stitch(const FileDesc* d_files, const ChainWs& ws, const u32* d_multi, u32 nmulti, hipStream_t st) {
+hipError_t launch_stitch(const FileDesc* d_files, const ChainWs& ws, const u32* d_multi, u32 nmulti, bool direct,
+                         hipStream_t st) {
   if (!nmulti) return hipSuccess;
-  hipLaunchKernelGGL(stitch_kernel, dim3(nmulti), dim3(kStitchThreads), 0, st, d_files, ws, d_multi, nmulti);
+  if (direct)
+    hipLaunchKernelGGL(stitch_kernel<DirectChain>, dim3(nmulti), dim3(kStitchThreads), 0, st, d_files, ws, d_multi,
+                       nmulti);
+  else
+    hipLaunchKernelGGL(stitch_kernel<MarkedChain>, dim3(nmulti), dim3(kStitchThreads), 0, st, d_files, ws, d_multi,
+                       nmulti);
   return hipGetLastError();
 }
 
-hipError_t launch_compact(const FileDesc* d_files, const ChainWs& ws, const u32* d_chains, u32 nchains, bool direct,
+hipError_t launch_compact(const FileDesc* d_files, const ChainWs& ws, const u32* d_chains, u32 nchains,
                           hipStream_t st) {
   if (!nchains) return hipSuccess;
   const u32 groups = (nchains + kWavesPerGroup - 1) / kWavesPerGroup;
-  if (direct)
-    hipLaunchKernelGGL(compact_kernel<DirectChain>, dim3(groups), dim3(256), 0, st, d_files, ws, d_chains, nchains);
-  else
-    hipLaunchKernelGGL(compact_kernel<MarkedChain>, dim3(groups), dim3(256), 0, st, d_files, ws, d_chains, nchains);
+  hipLaunchKernelGGL(compact_kernel, dim3(groups), dim3(256), 0, st, d_files, ws, d_chains, nchains);
   return hipGetLastError();
 }
 

@@ -59,6 +59,7 @@ struct Plan {
   std::mutex mu;
   DevBuf eo, esum, list, cont, chains, tables, flags, misc;
   DevBuf aux;        // calibration: candidates' cut lists and statistics
+  DevBuf ovf;        // overflow regions of open continuations the stitch takes further
   HostBuf staging, readback, aux_host;
   hipEvent_t call_done = nullptr, upload_done = nullptr;
   bool pending = false, upload_pending = false;

@@ -14,10 +14,12 @@ struct ChainWs {
   u64* conv_val;       // boundary k: first cut of chain k's continuation found in a later chain
   u32* conv_chain;     // segment (relative) whose list holds conv_val; nseg = reached the end
   i32* conv_idx;       // index of conv_val in that list; -1 = the segment start itself
-  u32* cont_cnt;       // continuation cuts before conv_val (may exceed cont_cap)
+  u64* cont_cnt;       // continuation cuts before conv_val (more than cont_cap once the stitch took it further)
   u64* cont;           // continuation cuts, cont_cap per multi-segment chain
   u64* cont_off;       // offset of each chain's continuation buffer in `cont`
-  u32 cont_cap;
+  u32 cont_cap;        // pass B stops a continuation whose buffer is full, leaving it open
+  u64* ovf;            // overflow regions (FileDesc::ovf0): cuts of open continuations taken further by the stitch
+  u64* ovf_start;      // where a chain's overflow cuts start in `ovf`
   u32* active;         // stitch: chain contributes to the output
   i32* entry_idx;      // stitch: index of the chain's first exact cut (-1 = segment start)
   u64* out_off;        // stitch: output offset of the chain's part

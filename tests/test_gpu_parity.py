@@ -183,6 +183,48 @@ def test_adversarial(env, tiny_plan, kind):
         _check(env, data, params, label=kind + "-default-seg")
 
 
+RUN7 = np.array([10, 20, 30, 40, 50, 5, 3], np.uint8)  # a 7-byte pattern holding a run of 5 increasing bytes
+
+
+def _open_cases():
+    """Streams whose continuations fill their buffers (1024 cuts at these parameters) before converging: in RUN7
+    repeated, every chunk ends just past a run, at the same phase of the pattern, so chunk lengths are multiples of
+    7 (4096 or 4101 bytes at min 4 KiB) that do not divide the segment length, and chains from different starts keep
+    different phases for ever."""
+    p7 = np.resize(RUN7, 32 << 20)
+    mixed = np.concatenate([np.resize(RUN7, 12 << 20), synth.uniform(8 << 20, seed=4), np.resize(RUN7[::-1], 6 << 20),
+                            synth.mixed(6 << 20, seed=6)])
+    return [("run7", p7), ("run7-then-random", mixed)]
+
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_open_continuations(env, tiny_plan, case):
+    """The stitch takes the open continuation on the exact path further (its overflow cuts), once per such chain;
+    the result is the oracle's.  64 KiB segments: about 8k cuts (min 4 KiB) and 16k cuts (min 2 KiB, SeqLength 3,
+    decreasing) against 1024-cut buffers."""
+    name, data = _open_cases()[case]
+    _check(env, data, P(), plan=tiny_plan, label="open-" + name)
+    _check(env, data, P(mode=1, sl=3, mn=2048, mx=8192, trig=9, skip=40), plan=tiny_plan, label="open2-" + name)
+
+
+@pytest.mark.parametrize("rmode", [0, 1])
+def test_open_continuations_in_a_batch(env, rmode):
+    torch, seq = env
+    datas = [d for _, d in _open_cases()] + [synth.mixed(3 << 20, seed=7), synth.uniform(70000, seed=8)]
+    params = [P()]
+    plan = seq.seqcdc_plan_create()
+    try:
+        seq.seqcdc_plan_set_tuning(plan, segment_bytes=64 << 10)
+        seq.seqcdc_plan_set_mode(plan, rmode)
+        tens = [torch.from_numpy(d).cuda() for d in datas]
+        _say("batch with open continuations, mode", rmode)
+        outs = seq.chunk_batch(tens, params, plan=plan)
+        for i, (d, o) in enumerate(zip(datas, outs)):
+            assert np.array_equal(o.cpu().numpy().astype(np.uint64), oracle.chunk(d, **params[0])), i
+    finally:
+        seq.seqcdc_plan_destroy(plan)
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 17, 63, 64, 65, 100, 1023, 1024, 1025, 4095, 4096, 4097, 65537,
                                (1 << 20) + 7])
 def test_small_and_ragged(env, n):
