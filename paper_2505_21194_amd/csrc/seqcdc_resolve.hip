@@ -90,7 +90,7 @@ struct MarkedChain {
   const uint4* eo;    // EO16 groups of the file
   const uint8_t* esum;
   u64 n;
-  u32 groups, nblocks;
+  u32 groups;
   u32 min_size, max_size, sl, trig, skip;
   u32 cur;            // sub-window held in E/O (kNone = none)
   u32 pf_base;        // bit i of pf_mask: the DMA of sub-window pf_base + i into its slot was issued
@@ -102,10 +102,12 @@ struct MarkedChain {
   u32 fe;             // lane l: first run-end bit of the group (64 = none)
   u32 total;          // opposing pairs in the whole window
   u64 emask;          // bit l: group l holds a run end
-  // summary knowledge: blocks [sum_from, sum_to) hold no run end; sum_hit says
-  // whether sum_to is a block with a run end (or the end) rather than a horizon
-  u32 sum_from, sum_to;
-  bool sum_hit, hot;
+  // summary knowledge, 0 = none, else (to << 1) | hit: the blocks from the
+  // last one asked about up to `to` hold no run end, and hit says whether
+  // `to` is a block with a run end (or the end) rather than a horizon.  A
+  // chain asks about blocks in increasing order, so the knowledge holds for
+  // every later question up to `to`.
+  u32 sumk;
 };
 
 constexpr u32 kNone = 0xFFFFFFFFu;
@@ -119,7 +121,6 @@ __device__ __forceinline__ void chain_init(MarkedChain& ch, const FileDesc& F, S
   ch.esum = F.esum;
   ch.n = F.n;
   ch.groups = (u32)((F.n + 63) >> 6);
-  ch.nblocks = (u32)((F.n + 1023) >> 10);
   ch.min_size = (u32)F.min_size;
   ch.max_size = (u32)F.max_size;
   ch.sl = F.sl;
@@ -132,9 +133,7 @@ __device__ __forceinline__ void chain_init(MarkedChain& ch, const FileDesc& F, S
   ch.incl = ch.excl = ch.total = 0;
   ch.fe = 64;
   ch.emask = 0;
-  ch.sum_from = ch.sum_to = 0;
-  ch.sum_hit = false;
-  ch.hot = false;
+  ch.sumk = 0;
 }
 
 // Starts the DMA of sub-window `sub` into its LDS slot (sub % kRing): lane l
@@ -192,20 +191,19 @@ __device__ __forceinline__ void ensure(MarkedChain& ch, u32 sub, u32 hint) {
   }
 }
 
-// Extend the summary knowledge from block b by one load (up to 1024 blocks,
-// 1 MiB of input): afterwards blocks [b, sum_to) are known to hold no run
-// end.
-__device__ void summary_extend(MarkedChain& ch, u32 b) {
+// One load of the summary from block b (up to 1024 blocks, 1 MiB of input):
+// `to` becomes the first block at or after b holding a run end (hit), or the
+// horizon of the load (blocks [b, to) hold no run end).
+__device__ __forceinline__ void summary_load(const uint8_t* esum, u32 nb, u32 b, u32& to, bool& hit) {
   const u32 lane = lane_id();
-  const u32 nb = ch.nblocks;
-  u32 to = b;
-  bool hit = b >= nb;
+  to = b;
+  hit = b >= nb;
   if (b < nb) {
     const u32 a = b & ~15u;
     const u32 idx = a + 16u * lane;
     // branch-free (keeps the chain state wave-uniform): every lane reads a valid
     // 16-byte chunk of the padded summary; bytes outside [b, nb) are masked
-    const uint4 v = load16(ch.esum + (idx < nb ? idx : ((nb - 1) & ~15u)));
+    const uint4 v = load16(esum + (idx < nb ? idx : ((nb - 1) & ~15u)));
     const u32 d[4] = {v.x, v.y, v.z, v.w};
     u32 m = 0;
 #pragma unroll
@@ -227,20 +225,29 @@ __device__ void summary_extend(MarkedChain& ch, u32 b) {
       hit = to >= nb;
     }
   }
-  if (!(ch.sum_from <= b && b <= ch.sum_to)) ch.sum_from = b;
-  ch.sum_to = to;
-  ch.sum_hit = hit;
-  ch.hot = true;
 }
+
+__device__ __forceinline__ bool summary_known(const MarkedChain& ch) { return ch.sumk != 0; }
 
 // True if no block in [b, ceil(L/1024)) holds a run end.  Uses and extends
 // the summary knowledge; cheap when it already covers b.  Block indices are
-// compared in 32 bits: sum_to * 1024 >= L exactly when sum_to >= ceil(L / 1024).
+// compared in 32 bits: to * 1024 >= L exactly when to >= ceil(L / 1024).
 __device__ __forceinline__ bool no_end_before(MarkedChain& ch, u32 b, u64 L) {
   const u32 lb = (u32)((L + 1023) >> 10);
-  if (!(ch.sum_from <= b && b <= ch.sum_to)) summary_extend(ch, b);
-  while (!ch.sum_hit && ch.sum_to < lb) summary_extend(ch, ch.sum_to);
-  return ch.sum_to >= lb;
+  u32 to = ch.sumk >> 1;
+  bool hit = ch.sumk & 1u;
+  u32 from = to;
+  if (!ch.sumk || b > to) {
+    from = b;
+    hit = false;
+    to = 0;
+  }
+  while (!hit && to < lb) {  // the first pass loads from b when the knowledge does not cover it
+    summary_load(ch.esum, (u32)((ch.n + 1023) >> 10), from, to, hit);
+    from = to;
+  }
+  ch.sumk = (to << 1) | (hit ? 1u : 0u);
+  return to >= lb;
 }
 
 // ---------------------------------------------------------------------------
@@ -411,6 +418,8 @@ __device__ __forceinline__ void ensure(DirectChain& ch, u32 w, u32 hint) {
   }
 }
 
+__device__ __forceinline__ bool summary_known(const DirectChain&) { return false; }
+
 // Group words: one lane's E or O bits.
 __device__ __forceinline__ u32 read_group(u32 v, u32 g) { return readlane(v, g); }
 __device__ __forceinline__ u64 read_group(u64 v, u32 g) { return readlane64(v, g); }
@@ -481,17 +490,24 @@ __device__ u64 next_cut(Ch& ch, u64 c) {
   u32 p = s + 1;                                                    // next pair (p-1, p) to examine
   u32 need = ch.trig;                                               // opposing pairs still to the trigger
   const u32 c32 = (u32)c;
+  // The run-end summary is asked (one place, so its code is inlined once)
+  // when the chunk starts inside a stretch already known to hold no run end
+  // (ask = 1, position: the earliest admissible run end), and after a whole
+  // window without a run end (ask = 2, position: the next window).  If no run
+  // end comes before the limit, the chunk ends there.
+  u32 ask = summary_known(ch) ? 1u : 0u;
+  u32 apos = s + ch.sl - 1;
   for (;;) {
     if (p >= lim) return c + lim;
     if constexpr (Ch::kSummary) {
-      if (ch.hot) {  // inside a stretch known to hold no run end: nothing to find before the limit?
-        const u32 e_lo = s + ch.sl - 1;
-        const u32 b = (u32)((c + (e_lo > p ? e_lo : p)) >> 10);
-        if (ch.sum_from <= b && b <= ch.sum_to) {
-          if (no_end_before(ch, b, c + lim)) return c + lim;
-        } else {
-          ch.hot = false;
+      if (ask) {
+        const u32 b = (u32)((c + apos) >> 10);
+        if (ask == 1 && b > (ch.sumk >> 1)) {
+          ch.sumk = 0;  // past the known stretch
+        } else if (no_end_before(ch, b, c + lim)) {
+          return c + lim;
         }
+        ask = 0;
       }
     }
     const u32 sub = (u32)((c + p) / kWin);
@@ -521,8 +537,9 @@ __device__ u64 next_cut(Ch& ch, u64 c) {
       need -= left;  // no event in this window
       p = w + kWin;
       if (p >= lim) return c + lim;
-      if constexpr (Ch::kSummary) {
-        if (no_end_before(ch, (u32)((c + p) >> 10), c + lim)) return c + lim;  // no run end before the limit
+      if (Ch::kSummary && ch.emask == 0) {  // random data never gets here
+        ask = 2;
+        apos = p;
       }
       break;
     }
