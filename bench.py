@@ -708,6 +708,8 @@ def main():
         extra["serving"].pop("_checks", None)
     if "dedup" in extra:
         extra["dedup"].pop("_check", None)
+    for case in extra.get("sweep", []):
+        case.pop("_check", None)
     out.update(extra)
     print(json.dumps(out), flush=True)
     seq.seqcdc_plan_destroy(plan)

@@ -12,7 +12,10 @@ and JSON summaries kept with the project:
   known size in the same run;
 * ``step FETCH_DB WRITE_DB``: the same for a whole chunking step, summed over
   every kernel the library launched in the run and divided by the number of
-  steps the run made (each step launches the same kernels once).
+  steps the run made (each step launches the same kernels once);
+* ``counters DB [DB ...]``: any other counters (one ``--pmc`` pass per
+  database), summed per kernel of the step, per step and per unit of work
+  (for instance per cut), as a short text table.
 
 Usage::
 
@@ -134,6 +137,20 @@ def step_traffic(fetch_db, write_db, steps, copy_kernel, copy_bytes):
                                                "fetch_scale": sf / 1024.0, "write_scale": sw / 1024.0}}
 
 
+def counter_table(dbs, steps, units):
+    """{kernel: {counter: value per step}} over the step's kernels, summed over each kernel's dispatches."""
+    acc = collections.OrderedDict((k, collections.OrderedDict()) for k in STEP_KERNELS)
+    for db in dbs:
+        con = sqlite3.connect(db)
+        rows = con.execute("select kernel_name, counter_name, sum(value) from counters_collection "
+                           "group by kernel_name, counter_name").fetchall()
+        for kn, cn, v in rows:
+            k = short_name(kn)
+            if k in acc:
+                acc[k][cn] = acc[k].get(cn, 0.0) + float(v) / steps
+    return {k: v for k, v in acc.items() if v}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -164,8 +181,26 @@ def main(argv=None):
     st.add_argument("--cmd-fetch", default="")
     st.add_argument("--cmd-write", default="")
     st.add_argument("--out", required=True)
+    cs = sub.add_parser("counters")
+    cs.add_argument("dbs", nargs="+")
+    cs.add_argument("--steps", type=int, required=True, help="chunking steps the profiled run made")
+    cs.add_argument("--units", type=float, default=0, help="units of work per step (e.g. cuts) for per-unit columns")
+    cs.add_argument("--unit-name", default="cut")
+    cs.add_argument("--title", default="")
+    cs.add_argument("--commands", nargs="*", default=[])
     a = ap.parse_args(argv)
-    if a.cmd == "stats":
+    if a.cmd == "counters":
+        if a.title:
+            print(a.title)
+        for c in a.commands:
+            print("command: " + c)
+        print("per step%s; SQ_*CYCLES and SQ_WAIT_* count 4-cycle units" %
+              (" and per %s (%d %ss per step)" % (a.unit_name, a.units, a.unit_name) if a.units else ""))
+        for k, cnt in counter_table(a.dbs, a.steps, a.units).items():
+            print(k)
+            for cn, v in cnt.items():
+                print("  %-24s %16.0f%s" % (cn, v, ("  %12.2f" % (v / a.units)) if a.units else ""))
+    elif a.cmd == "stats":
         if a.title:
             print(a.title)
         if a.command:

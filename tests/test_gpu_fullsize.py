@@ -5,7 +5,8 @@
   8 KiB parameters at SeqLength 6 in both modes.
 * A 256 MiB uniform base plus 9 versions of 200 seeded edits each, chunked in one batch at 4..64 KiB averages:
   every boundary list and the space savings of Eq. 1.
-* 512 MiB uniform in 64 KiB segments: more covered ranges than the stitch keeps in LDS.
+* 512 MiB uniform in 64 KiB segments: more jumps and covered ranges than the stitch keeps in LDS.
+* 160 MiB of alternating segment kinds in 64 KiB segments: jumps resolved in LDS, covered ranges beyond it.
 * 4096 files with log-normal sizes (median 256 KiB, sigma 1.5, 4 KiB..64 MiB), each a mixed stream of its own
   seed, at a 16 KiB average: the eager batched call and its prepared hipGraph replay.
 The plain streams and the 4096-file batch also run in the direct (skip-aware) resolve mode.
@@ -15,6 +16,7 @@ import pytest
 
 import oracle
 import synth
+from tests import stitch_cases
 
 pytestmark = pytest.mark.gpu
 
@@ -97,6 +99,28 @@ def test_many_covered_ranges_512mib(env, mode):
         seq.seqcdc_plan_set_tuning(plan, segment_bytes=64 << 10)
         seq.seqcdc_plan_set_mode(plan, mode)
         _say("512 MiB uniform, 64 KiB segments, mode", mode)
+        got = seq.chunk(dev, p, plan=plan).cpu().numpy().astype(np.uint64)
+    finally:
+        seq.seqcdc_plan_destroy(plan)
+    want = oracle.chunk(host, **_pd(p))
+    assert got.size == want.size and np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_lds_jumps_many_ranges_160mib(env, mode):
+    """160 MiB alternating fast-resynchronising and never-resynchronising 64 KiB segments: 1280 jumps, at most
+    the 2048 the stitch resolves in LDS in parallel, all active, more than the 1024 covered ranges it keeps in
+    LDS, so its range search reads the covered ranges from global memory (counts from oracle paths in
+    test_stitch_cases.py)."""
+    torch, seq = env
+    host = stitch_cases.alternating(160 << 20, 64 << 10)
+    dev = torch.from_numpy(host).cuda()
+    p = seq.seqcdc_params_for_avg(8192)
+    plan = seq.seqcdc_plan_create()
+    try:
+        seq.seqcdc_plan_set_tuning(plan, segment_bytes=64 << 10)
+        seq.seqcdc_plan_set_mode(plan, mode)
+        _say("160 MiB alternating segments, 64 KiB segments, mode", mode)
         got = seq.chunk(dev, p, plan=plan).cpu().numpy().astype(np.uint64)
     finally:
         seq.seqcdc_plan_destroy(plan)
