@@ -149,8 +149,8 @@ def batched(seq, torch, stream, plan, steps, warmup, dev, tune):
         seq.seqcdc_chunk_batch(ftab, [pb], bcuts.data_ptr(), otab, bcounts.data_ptr(), stream=stream, plan=plan)
 
     tuning = None
-    if tune:  # the autotuner on the batch's bytes taken as one stream, at the batch's parameters (untimed)
-        seq.seqcdc_autotune(plan, buf.data_ptr(), total, pb, stream=stream)
+    if tune:  # the library's batch autotuner on this batch (untimed): it sets the plan's settings
+        seq.seqcdc_autotune_batch(plan, ftab, [pb], bcuts.data_ptr(), otab, bcounts.data_ptr(), stream=stream)
         seg, span, waves = seq.seqcdc_plan_get_tuning(plan, total, pb)
         tuning = {"segment_bytes": seg, "mark_span_blocks": span, "waves_per_cu": waves}
         log("batched tuning: %s" % tuning)

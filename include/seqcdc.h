@@ -176,6 +176,20 @@ int seqcdc_chunk_batch(seqcdc_plan* plan, const seqcdc_file* h_files, uint32_t n
                        uint32_t nparams, uint64_t* d_cuts, const uint64_t* h_cut_offsets, uint64_t* d_counts,
                        void* stream);
 
+/* Autotuner for a batch: times candidate segment lengths (multiples of the
+ * smallest min_size), mark spans, chain occupancies and both resolve modes on
+ * seqcdc_chunk_batch itself with the given arguments (as for that call), and
+ * sets the fastest as the plan's own settings (those seqcdc_plan_set_tuning
+ * and seqcdc_plan_set_mode set; they replace earlier ones and take precedence
+ * over the process-wide cache).  The best settings for many files differ from
+ * those for one stream of the same parameters.  Synchronous; the batch's
+ * outputs hold its results when it returns.  Results are exact for every
+ * choice; only speed differs.  *best_ms receives the best time (may be NULL).
+ * Errors as for seqcdc_chunk_batch; SEQCDC_EINVAL for an empty batch. */
+int seqcdc_autotune_batch(seqcdc_plan* plan, const seqcdc_file* h_files, uint32_t nfiles, const seqcdc_params* h_params,
+                          uint32_t nparams, uint64_t* d_cuts, const uint64_t* h_cut_offsets, uint64_t* d_counts,
+                          double* best_ms, void* stream);
+
 /* Prepared batches, for callers that chunk the same set of device buffers
  * again and again (a ring of staging buffers refilled with new data, a fixed
  * set of volumes).  seqcdc_batch_prepare lays the batch out once, in a

@@ -92,6 +92,8 @@ _SIGS = {
                           ctypes.c_int),
     "seqcdc_chunk_batch": ([_p, ctypes.POINTER(seqcdc_file), _u32, ctypes.POINTER(seqcdc_params), _u32, _p,
                             ctypes.POINTER(_u64), _p, _p], ctypes.c_int),
+    "seqcdc_autotune_batch": ([_p, ctypes.POINTER(seqcdc_file), _u32, ctypes.POINTER(seqcdc_params), _u32, _p,
+                               ctypes.POINTER(_u64), _p, ctypes.POINTER(ctypes.c_double), _p], ctypes.c_int),
     "seqcdc_batch_prepare": ([_p, ctypes.POINTER(seqcdc_file), _u32, ctypes.POINTER(seqcdc_params), _u32, _p,
                               ctypes.POINTER(_u64), _p, ctypes.POINTER(_p)], ctypes.c_int),
     "seqcdc_batch_launch": ([_p, _p], ctypes.c_int),
@@ -220,6 +222,23 @@ def seqcdc_autotune(plan, d_sample, n, params, stream=None):
     ms = ctypes.c_double()
     _check(lib.seqcdc_autotune(plan, d_sample, n, ctypes.byref(_as_params(params)), ctypes.byref(ms),
                                _stream_handle(stream)))
+    return ms.value
+
+
+def seqcdc_autotune_batch(plan, files, params_list, d_cuts, cut_offsets, d_counts, stream=None):
+    """Tunes `plan` for this batch (arguments as for seqcdc_chunk_batch); returns the best time in ms."""
+    if isinstance(files, ctypes.Array):
+        farr, nf = files, getattr(files, "_len", len(files))
+    else:
+        farr = file_table([f[0] for f in files], [f[1] for f in files], [f[2] for f in files])
+        nf = len(files)
+    parr = (seqcdc_params * max(len(params_list), 1))(*[_as_params(p) for p in params_list])
+    offs = cut_offsets if isinstance(cut_offsets, ctypes.Array) else offsets_table(cut_offsets)
+    if len(offs) < nf + 1:
+        raise ValueError("cut_offsets needs nfiles + 1 entries")
+    ms = ctypes.c_double()
+    _check(lib.seqcdc_autotune_batch(plan, farr, nf, parr, len(params_list), d_cuts, offs, d_counts,
+                                     ctypes.byref(ms), _stream_handle(stream)))
     return ms.value
 
 

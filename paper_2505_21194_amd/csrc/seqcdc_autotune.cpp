@@ -1,8 +1,10 @@
 // Autotuner: picks the segment length of speculative resolution, the mark
 // span, the waves per CU of the persistent chain kernels and the resolve mode
 // (marked or direct) by timing candidates on a device-resident sample.  Every candidate produces the same
-// cuts; only speed differs.  Results go to a process-wide cache keyed by
-// (arch, CU count, SeqLength, average class).
+// cuts; only speed differs.  A single stream's results go to a process-wide
+// cache keyed by (arch, CU count, SeqLength, average class); a batch's results
+// become the plan's own settings, since the best settings for many files
+// differ from those for one stream of the same parameters.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,6 +25,29 @@ static int time_config(Plan* pl, const void* d, u64 n, const seqcdc_params* p, u
     hipError_t e = hipEventRecord(e0, st);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     rc = chunk_plan(pl, d, n, p, d_cuts, cap, &cnt, st);
+    if (rc) return rc;
+    e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e != hipSuccess) return hip_fail(e, "hipEvent timing");
+    best = std::min(best, (double)t);
+  }
+  *ms = best;
+  return SEQCDC_OK;
+}
+
+// Best of `reps` timed batched calls (after one untimed call).
+static int time_batch(Plan* pl, const seqcdc_file* files, u32 nfiles, const seqcdc_params* params, u32 nparams,
+                      u64* d_cuts, const u64* h_offs, u64* d_counts, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+                      int reps, double* ms) {
+  int rc = chunk_batch(pl, files, nfiles, params, nparams, d_cuts, h_offs, d_counts, st);
+  if (rc) return rc;
+  double best = 1e30;
+  for (int r = 0; r < reps; r++) {
+    hipError_t e = hipEventRecord(e0, st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    rc = chunk_batch(pl, files, nfiles, params, nparams, d_cuts, h_offs, d_counts, st);
     if (rc) return rc;
     e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -115,5 +140,78 @@ extern "C" int seqcdc_autotune(seqcdc_plan* plan, const void* d_sample, uint64_t
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(d_cuts);
+  return rc;
+}
+
+extern "C" int seqcdc_autotune_batch(seqcdc_plan* plan, const seqcdc_file* h_files, uint32_t nfiles,
+                                     const seqcdc_params* h_params, uint32_t nparams, uint64_t* d_cuts,
+                                     const uint64_t* h_cut_offsets, uint64_t* d_counts, double* best_ms,
+                                     void* stream) {
+  if (!plan) return fail(SEQCDC_EINVAL, "plan is NULL");
+  if (!h_files || !h_params || !h_cut_offsets || nfiles == 0 || nparams == 0)
+    return fail(SEQCDC_EINVAL, "empty batch");
+  int rc;
+  u64 min_min = ~0ull;
+  for (u32 i = 0; i < nparams; i++) {
+    if ((rc = validate(&h_params[i]))) return rc;
+    min_min = std::min<u64>(min_min, h_params[i].min_size);
+  }
+  Plan* pl = (Plan*)plan;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const u64 saved_seg = pl->seg_override;
+  const u32 saved_span = pl->span_override, saved_waves = pl->waves_override;
+  const int saved_mode = pl->mode;
+  double best = 1e30;
+  u64 best_seg = 0;
+  u32 best_span = 16, best_waves = 12;
+  int best_mode = 0;
+  auto trial = [&](u64 seg, u32 span, u32 waves, int mode) -> int {
+    pl->seg_override = seg;
+    pl->span_override = span;
+    pl->waves_override = waves;
+    pl->mode = mode;
+    double ms = 0;
+    int r = time_batch(pl, h_files, nfiles, h_params, nparams, d_cuts, h_cut_offsets, d_counts, st, e0, e1, 3, &ms);
+    if (r) return r;
+    if (ms < best) {
+      best = ms;
+      best_seg = seg;
+      best_span = span;
+      best_waves = waves;
+      best_mode = mode;
+    }
+    return SEQCDC_OK;
+  };
+  // coordinate search over the batch itself: segment length (multiples of
+  // the smallest min_size), mark span, chain occupancy, then the direct mode
+  rc = SEQCDC_OK;
+  for (u64 m : {16ull, 32ull, 64ull, 128ull, 256ull})
+    if ((rc = trial(m * min_min, 16, 12, 0))) break;
+  if (!rc)
+    for (u32 s : {8u, 32u})
+      if ((rc = trial(best_seg, s, 12, 0))) break;
+  if (!rc) {
+    const u32 s = best_span;
+    for (u32 w : {8u, 16u, 20u})
+      if ((rc = trial(best_seg, s, w, 0))) break;
+  }
+  if (!rc) rc = trial(best_seg, best_span, 12, 1);
+  if (!rc) {  // the plan keeps the fastest settings
+    pl->seg_override = best_seg;
+    pl->span_override = best_span;
+    pl->waves_override = best_waves;
+    pl->mode = best_mode;
+    if (best_ms) *best_ms = best;
+  } else {
+    pl->seg_override = saved_seg;
+    pl->span_override = saved_span;
+    pl->waves_override = saved_waves;
+    pl->mode = saved_mode;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   return rc;
 }

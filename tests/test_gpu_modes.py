@@ -54,6 +54,59 @@ def test_autotune_keeps_results(env):
         seq.seqcdc_plan_destroy(plan)
 
 
+def _pd(p):
+    return dict(mode=p.mode, seq_length=p.seq_length, min_size=p.min_size, max_size=p.max_size,
+                skip_trigger=p.skip_trigger, skip_size=p.skip_size)
+
+
+def test_autotune_batch_keeps_results(env):
+    """The batch autotuner times the batched call over these files and sets the plan's settings; the batch and a
+    prepared batch with those settings then give the oracle's cuts for every file."""
+    torch, seq = env
+    sizes = synth.lognormal_sizes(48, 256 * 1024, 1.5, 4096, 8 << 20, seed=33).astype(np.int64)
+    datas = [synth.mixed(int(n), seed=500 + i) for i, n in enumerate(sizes)]
+    tens = [torch.from_numpy(x).cuda() for x in datas]
+    p16, p8 = seq.seqcdc_params_for_avg(16384), seq.seqcdc_params_for_avg(8192)
+    params = [p16, p8]
+    pidx = [i % 2 for i in range(len(tens))]
+    offs = [0]
+    for t, k in zip(tens, pidx):
+        offs.append(offs[-1] + seq.seqcdc_max_cuts(t.numel(), params[k]))
+    cuts = torch.empty(offs[-1], dtype=torch.int64, device="cuda")
+    counts = torch.empty(len(tens), dtype=torch.int64, device="cuda")
+    files = [(t.data_ptr(), t.numel(), k) for t, k in zip(tens, pidx)]
+    wants = [oracle.chunk(x, **_pd(params[k])) for x, k in zip(datas, pidx)]
+
+    def check(label):
+        torch.cuda.synchronize()
+        c = counts.cpu().numpy()
+        allc = cuts.cpu().numpy().astype(np.uint64)
+        for i, w in enumerate(wants):
+            got = allc[offs[i]:offs[i] + int(c[i])]
+            assert got.size == w.size and np.array_equal(got, w), (label, i)
+
+    plan = seq.seqcdc_plan_create()
+    try:
+        _say("batch autotune, 48 files, two parameter sets")
+        ms = seq.seqcdc_autotune_batch(plan, files, params, cuts.data_ptr(), offs, counts.data_ptr())
+        assert ms > 0
+        check("tuning")
+        cuts.fill_(0)
+        counts.fill_(0)
+        seq.seqcdc_chunk_batch(files, params, cuts.data_ptr(), offs, counts.data_ptr(), plan=plan)
+        check("tuned batch")
+        cuts.fill_(0)
+        counts.fill_(0)
+        b = seq.seqcdc_batch_prepare(files, params, cuts.data_ptr(), offs, counts.data_ptr(), settings=plan)
+        try:
+            seq.seqcdc_batch_launch(b)
+            check("tuned prepared batch")
+        finally:
+            seq.seqcdc_batch_destroy(b)
+    finally:
+        seq.seqcdc_plan_destroy(plan)
+
+
 @pytest.mark.parametrize("avg_kib", [4, 8, 16, 32, 64])
 def test_snapshot_dedup_matches_oracle(env, avg_kib):
     torch, seq = env
