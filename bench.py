@@ -141,6 +141,43 @@ def batch_workload(seq, torch, dev):
     return buf, sizes, total, pb, cut_offs, bcuts, bcounts, files, ftab, otab
 
 
+def pipelined_batches(seq, torch, stream, plan, ftab, pb, otab, bcuts, bcounts, total, steps, warmup):
+    """The batch with two calls in flight: the given plan on `stream` and a second plan on a second stream (default
+    priority), each writing its own outputs, the calls alternating.  Rate = batches x bytes over the time of 2*steps
+    calls; both output sets are compared with the eager call's afterwards."""
+    torch.cuda.synchronize()
+    want_cuts, want_counts = bcuts.cpu().numpy(), bcounts.cpu().numpy()
+    side = torch.cuda.Stream()
+    plan2 = seq.seqcdc_plan_create()
+    cuts2, counts2 = torch.empty_like(bcuts), torch.empty_like(bcounts)
+    try:
+        seq.seqcdc_autotune_batch(plan2, ftab, [pb], cuts2.data_ptr(), otab, counts2.data_ptr(), stream=side)
+        torch.cuda.synchronize()
+        lanes = [(plan, stream, bcuts, bcounts), (plan2, side, cuts2, counts2)]
+
+        def call(i):
+            pl, st, c, n = lanes[i & 1]
+            seq.seqcdc_chunk_batch(ftab, [pb], c.data_ptr(), otab, n.data_ptr(), stream=st, plan=pl)
+        for i in range(2 * warmup):
+            call(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(2 * steps):
+            call(i)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / (2 * steps)
+        same = all(bool(np.array_equal(c.cpu().numpy(), want_cuts) and np.array_equal(n.cpu().numpy(), want_counts))
+                   for _, _, c, n in lanes)
+    finally:
+        seq.seqcdc_plan_destroy(plan2)
+    traffic = stored_step_traffic("batched")
+    out = {"in_flight": 2, "ms_per_batch": round(dt * 1e3, 3), "GBps": round(total / dt / 1e9, 1),
+           "outputs_match": same}
+    if traffic:  # counter bytes of one batch step over the time per batch
+        out["traffic_frac"] = round(traffic / dt / 1e9 / HBM_PEAK_GBS, 4)
+    return out
+
+
 def batched(seq, torch, stream, plan, steps, warmup, dev, tune):
     nfiles = 4096
     buf, sizes, total, pb, cut_offs, bcuts, bcounts, files, ftab, otab = batch_workload(seq, torch, dev)
@@ -178,6 +215,9 @@ def batched(seq, torch, stream, plan, steps, warmup, dev, tune):
         graph_same = bool(np.array_equal(bcounts.cpu().numpy(), counts))
     finally:
         seq.seqcdc_batch_destroy(gb)
+    # two batches in flight: a second plan (tuned the same way) on its own stream with its own outputs, the calls
+    # alternating between the two, so one batch's resolve overlaps the next one's marking
+    pipelined = pipelined_batches(seq, torch, stream, plan, ftab, pb, otab, bcuts, bcounts, total, steps, warmup)
     # one plain launch per file, the same files and parameters
     pcap = max(cut_offs[i + 1] - cut_offs[i] for i in range(nfiles))
     for f in range(16):
@@ -216,7 +256,7 @@ def batched(seq, torch, stream, plan, steps, warmup, dev, tune):
     del buf, bcuts
     return {"files": nfiles, "bytes": total, "cuts": int(counts.sum()), "ms_per_step": round(bdt * 1e3, 3),
             "GBps": round(total / bdt / 1e9, 1), "frac_hbm_peak_input": round(total / bdt / 1e9 / HBM_PEAK_GBS, 4),
-            "roofline": roof, "direct": direct,
+            "roofline": roof, "direct": direct, "pipelined": pipelined,
             "graph_ms_per_step": round(gdt * 1e3, 3), "graph_GBps": round(total / gdt / 1e9, 1),
             "graph_counts_match": graph_same,
             "per_file_launch_GBps": round(total / pdt / 1e9, 2), "speedup_vs_per_file": round(pdt / bdt, 2),

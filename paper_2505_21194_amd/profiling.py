@@ -46,10 +46,16 @@ def source_digest(paths=MARK_SOURCES):
     return h.hexdigest()
 
 
+# sources of a chunking step: its kernels, their launchers and the runtime that lays a call out (the autotuner,
+# serving loop, dedup, calibration and graph capture only choose settings or run other work)
+STEP_SOURCES = ("csrc/seqcdc_api.cpp", "csrc/seqcdc_device.h", "csrc/seqcdc_internal.h", "csrc/seqcdc_launch.h",
+                "csrc/seqcdc_mark.h", "csrc/seqcdc_mark.hip", "csrc/seqcdc_resolve.hip", "csrc/seqcdc_runtime.h",
+                "csrc/seqcdc_workspace.h")
+
+
 def all_sources_digest():
-    """Digest of every kernel and runtime source: a whole-step measurement holds while none changes."""
-    d = os.path.join(HERE, "csrc")
-    return source_digest(tuple("csrc/" + f for f in sorted(os.listdir(d))))
+    """Digest of the step's sources: a whole-step measurement holds while none of them changes."""
+    return source_digest(STEP_SOURCES)
 
 
 def short_name(name):
