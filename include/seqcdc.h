@@ -304,7 +304,9 @@ int seqcdc_dedup_batch(seqcdc_plan* plan, const seqcdc_file* h_files, uint32_t n
  * pass while their bytes fit its capacity and a ring slot is free, launches
  * each admitted group as one batched pass on the pass's HIP stream (groups
  * overlap on the GPU), and publishes each request's cuts and latency when its
- * pass completes.  The oldest queued request is never overtaken.
+ * pass completes.  The oldest queued request is never overtaken.  When
+ * several passes are free, each takes an equal share of the queued bytes, so
+ * a backlog runs as passes in flight together.
  * Passes use the phased resolve launches without overlapped groups and 8
  * chain waves per compute unit; segment length and mark span follow the
  * autotuner's choices, if any. 

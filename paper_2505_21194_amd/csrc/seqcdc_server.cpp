@@ -186,10 +186,21 @@ static void scheduler(Server* s) {
       std::unique_lock<std::mutex> lk(s->mu);
       if (s->stop && s->queue.empty() && !any_busy) return;
       if (free_pass) {
+        // With several passes free, each takes an equal share of the queued
+        // bytes, so a backlog runs as passes in flight together (one pass's
+        // resolve overlaps another's marking) rather than as one large pass.
+        u32 nfree = 0;
+        for (Pass* ps : s->passes) nfree += ps->busy ? 0u : 1u;
+        u64 limit = s->pass_cap;
+        if (nfree > 1) {
+          u64 queued = 0;
+          for (Request* r : s->queue) queued += r->cost;
+          limit = std::min<u64>(limit, (queued + nfree - 1) / nfree);
+        }
         for (auto it = s->queue.begin(); it != s->queue.end() && group.size() < s->cfg.max_batch;) {
           Request* r = *it;
-          const bool fits = group_bytes + r->cost <= s->pass_cap &&
-                            s->reqs_inflight + group.size() < s->cfg.ring_slots;
+          const bool room = group.empty() ? r->cost <= s->pass_cap : group_bytes + r->cost <= limit;
+          const bool fits = room && s->reqs_inflight + group.size() < s->cfg.ring_slots;
           if (fits) {
             group.push_back(r);
             group_bytes += r->cost;
