@@ -85,8 +85,9 @@ __device__ __forceinline__ void sha256_block(u32 st[8], u32 w[16]) {
 
 // The 16 big-endian message words of the 64 bytes at p (p + 64 <= end), or
 // of the last part of a message: the bytes [p, end) followed, when `pad`, by
-// the 0x80 byte at end - p (< 64) and zeros.  Only aligned words that hold a
-// byte below `end` are read: such a word never crosses a page end.
+// the 0x80 byte at end - p (< 64) and zeros; all zeros when p > end.  Only
+// aligned words that hold a byte below `end` are read: such a word never
+// crosses a page end.
 __device__ __forceinline__ void load_words(const uint8_t* p, const uint8_t* end, bool pad, u32 w[16]) {
   const uintptr_t a = (uintptr_t)p;
   const u32 sh = (u32)(a & 3);
@@ -95,7 +96,12 @@ __device__ __forceinline__ void load_words(const uint8_t* p, const uint8_t* end,
   u32 d[17];
 #pragma unroll
   for (int j = 0; j < 17; j++) d[j] = (a - sh + 4 * j < e) ? base[j] : 0u;
-  const u32 valid = e - a < 64 ? (u32)(e - a) : 64u;
+  // message bytes from p: none when p is past the end (the aligned word read
+  // first may still hold the message's last bytes; they are masked off)
+  const bool inside = a <= e;
+  const uintptr_t left = inside ? e - a : 0;
+  const u32 valid = left < 64 ? (u32)left : 64u;
+  const bool pad_here = pad && inside && left < 64;  // the 0x80 byte falls in this block
 #pragma unroll
   for (int k = 0; k < 16; k++) {
     u32 x = __builtin_amdgcn_alignbyte(d[k + 1], d[k], sh);  // bytes 4k .. 4k+3 from p, little-endian
@@ -103,37 +109,10 @@ __device__ __forceinline__ void load_words(const uint8_t* p, const uint8_t* end,
     if (o + 4 > valid) {  // the word holds the end of the message
       const u32 keep = valid > o ? valid - o : 0;  // 0..3 message bytes
       x = keep ? x & ((1u << (8 * keep)) - 1u) : 0u;
-      if (pad && valid >= o && valid < o + 4) x |= 0x80u << (8 * (valid - o));
+      if (pad_here && valid >= o && valid < o + 4) x |= 0x80u << (8 * (valid - o));
     }
     w[k] = bswap32(x);
   }
-}
-
-// SHA-256 of the len bytes at p.
-__device__ void sha256(const uint8_t* p, u64 len, u32 out[8]) {
-  u32 st[8];
-#pragma unroll
-  for (int i = 0; i < 8; i++) st[i] = kSha256H0[i];
-  const uint8_t* end = p + len;
-  u32 w[16];
-  u64 full = len >> 6;
-  for (u64 b = 0; b < full; b++) {
-    load_words(p + 64 * b, end, false, w);
-    sha256_block(st, w);
-  }
-  // the rest of the message, the 0x80 byte and the 64-bit bit length
-  const u32 rest = (u32)(len & 63);
-  load_words(p + 64 * full, end, true, w);
-  if (rest >= 56) {  // no room for the length in this block
-    sha256_block(st, w);
-#pragma unroll
-    for (int k = 0; k < 16; k++) w[k] = 0;
-  }
-  w[14] = (u32)((len * 8) >> 32);
-  w[15] = (u32)(len * 8);
-  sha256_block(st, w);
-#pragma unroll
-  for (int i = 0; i < 8; i++) out[i] = st[i];
 }
 
 // The 16 bytes at p + off .. (fewer where the chunk [p, p + len) ends; the
@@ -187,18 +166,100 @@ __device__ __forceinline__ bool chunk_of(const DedupFile* __restrict__ files, u3
   return true;
 }
 
-// Pass 1: the fingerprint of every chunk (one thread each).
-__global__ __launch_bounds__(256) void sha_kernel(const DedupFile* __restrict__ files, u32 nfiles,
-                                                  const u64* __restrict__ cuts, u64 nslots, u32* digests) {
-  const u64 slot = (u64)blockIdx.x * 256 + threadIdx.x;
-  if (slot >= nslots) return;
-  const uint8_t* data;
-  u64 start, end;
-  u32 h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (chunk_of(files, nfiles, cuts, slot, data, start, end)) sha256(data + start, end - start, h);
-  uint4* dst = (uint4*)(digests + 8 * slot);
-  dst[0] = make_uint4(h[0], h[1], h[2], h[3]);
-  dst[1] = make_uint4(h[4], h[5], h[6], h[7]);
+// Block b of the padded message of the len bytes at p (FIPS 180-4 Sec.
+// 5.1.1): the message bytes, the 0x80 byte right after them, zeros, and the
+// 64-bit bit length in the last 8 bytes of the last of the nb blocks.  The
+// same code serves every block (load_words reads nothing at or past the end
+// and puts the 0x80 byte where the message ends inside the block).
+__device__ __forceinline__ void padded_block(const uint8_t* p, u64 len, u64 b, u64 nb, u32 w[16]) {
+  load_words(p + 64 * b, p + len, true, w);
+  if (b + 1 == nb) {
+    w[14] = (u32)((len * 8) >> 32);
+    w[15] = (u32)(len * 8);
+  }
+}
+
+// Pass 1 with balanced lanes: each lane hashes chunk after chunk, and every
+// step hashes one block of each lane's current message, so the lanes of a
+// wave stay busy however the chunk lengths of neighbouring slots differ.  A
+// wave takes slots from the global queue kBatch at a time (every lane
+// executes that atomic, lane 0 adding kBatch, in wave-uniform control flow)
+// and hands them to its idle lanes in lane order (ranks by mbcnt).  Slots past
+// a file's count get a zero digest.  A wave ends once the queue is empty and
+// its lanes have finished: every step either hashes a block or takes slots.
+constexpr u32 kShaBatch = 64;
+
+__global__ __launch_bounds__(256) void sha_queue_kernel(const DedupFile* __restrict__ files, u32 nfiles,
+                                                        const u64* __restrict__ cuts, u64 nslots, u32* digests,
+                                                        unsigned long long* next) {
+  u64 wb = 0, we = 0;      // wave-uniform: the wave's batch of slots [wb, we)
+  bool exhausted = false;  // wave-uniform: the queue had no slot left
+  u64 slot = 0;
+  const uint8_t* p = nullptr;
+  u64 len = 0, b = 0, nb = 1;
+  bool busy = false;
+  u32 st[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) st[i] = 0;
+  for (;;) {
+    const u64 need = ballot(!busy);
+    if (need && !exhausted) {
+      if (wb == we) {
+        const unsigned long long v = atomicAdd(next, lane_id() == 0 ? (unsigned long long)kShaBatch : 0ull);
+        wb = readlane64((u64)v, 0);
+        we = wb + kShaBatch;
+        if (wb >= nslots) exhausted = true;
+      }
+      if (!exhausted) {
+        const u64 avail = we - wb;
+        const u32 rank = __builtin_amdgcn_mbcnt_hi((u32)(need >> 32), __builtin_amdgcn_mbcnt_lo((u32)need, 0u));
+        if (!busy && rank < avail) {
+          slot = wb + rank;
+          if (slot < nslots) {
+            const uint8_t* data;
+            u64 start, end;
+            if (chunk_of(files, nfiles, cuts, slot, data, start, end)) {
+              p = data + start;
+              len = end - start;
+              b = 0;
+              nb = (len + 8) / 64 + 1;
+              busy = true;
+#pragma unroll
+              for (int i = 0; i < 8; i++) st[i] = kSha256H0[i];
+            } else {  // past its file's count
+              uint4* dst = (uint4*)(digests + 8 * slot);
+              dst[0] = make_uint4(0, 0, 0, 0);
+              dst[1] = make_uint4(0, 0, 0, 0);
+            }
+          }
+        }
+        const u64 k = (u64)__popcll(need);
+        wb += k < avail ? k : avail;
+      }
+    }
+    if (!ballot(busy)) {
+      if (exhausted) break;  // no slot left and no lane busy
+      continue;              // the slots taken were past their files' counts: take more
+    }
+    // one block of every busy lane's message; idle lanes read nothing (empty message)
+    u32 w[16];
+    padded_block(busy ? p : nullptr, busy ? len : 0, busy ? b : 0, busy ? nb : 1, w);
+    u32 s2[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) s2[i] = st[i];
+    sha256_block(s2, w);
+    if (busy) {
+#pragma unroll
+      for (int i = 0; i < 8; i++) st[i] = s2[i];
+      b++;
+      if (b == nb) {
+        uint4* dst = (uint4*)(digests + 8 * slot);
+        dst[0] = make_uint4(st[0], st[1], st[2], st[3]);
+        dst[1] = make_uint4(st[4], st[5], st[6], st[7]);
+        busy = false;
+      }
+    }
+  }
 }
 
 constexpr u32 kNoOwner = 0xFFFFFFFFu;
@@ -361,11 +422,14 @@ extern "C" int seqcdc_dedup_batch(seqcdc_plan* plan, const seqcdc_file* h_files,
   const u32 grid = (u32)((nslots + 255) / 256);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(zero64_kernel, dim3(1024), dim3(256), 0, st, table, cap + 2);
-    hipLaunchKernelGGL(zero64_kernel, dim3(1), dim3(256), 0, st, totals, (u64)2);
+    hipLaunchKernelGGL(zero64_kernel, dim3(1), dim3(256), 0, st, totals, (u64)3);  // orig, unique, SHA queue
     e = hipGetLastError();
   }
   if (e == hipSuccess && nslots) {
-    hipLaunchKernelGGL(sha_kernel, dim3(grid), dim3(256), 0, st, d_files, nfiles, cuts, nslots, digests);
+    // four waves per SIMD, fewer for small calls (each lane hashes several chunks)
+    const u32 sha_groups = (u32)std::max<u64>(1, std::min<u64>((u64)pl->cus * 4, (nslots + 255) / 256));
+    hipLaunchKernelGGL(sha_queue_kernel, dim3(sha_groups), dim3(256), 0, st, d_files, nfiles, cuts, nslots, digests,
+                       (unsigned long long*)(totals + 2));
     hipLaunchKernelGGL(insert_kernel, dim3(grid), dim3(256), 0, st, d_files, nfiles, cuts, nslots,
                        (const u32*)digests, table, cap - 1, owner);
     hipLaunchKernelGGL(verify_kernel, dim3((u32)((nslots + kWavesPerGroup - 1) / kWavesPerGroup)), dim3(256), 0, st,
