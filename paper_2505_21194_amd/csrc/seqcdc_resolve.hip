@@ -227,8 +227,6 @@ __device__ __forceinline__ void summary_load(const uint8_t* esum, u32 nb, u32 b,
   }
 }
 
-__device__ __forceinline__ bool summary_known(const MarkedChain& ch) { return ch.sumk != 0; }
-
 // True if no block in [b, ceil(L/1024)) holds a run end.  Uses and extends
 // the summary knowledge; cheap when it already covers b.  Block indices are
 // compared in 32 bits: to * 1024 >= L exactly when to >= ceil(L / 1024).
@@ -418,8 +416,6 @@ __device__ __forceinline__ void ensure(DirectChain& ch, u32 w, u32 hint) {
   }
 }
 
-__device__ __forceinline__ bool summary_known(const DirectChain&) { return false; }
-
 // Group words: one lane's E or O bits.
 __device__ __forceinline__ u32 read_group(u32 v, u32 g) { return readlane(v, g); }
 __device__ __forceinline__ u64 read_group(u64 v, u32 g) { return readlane64(v, g); }
@@ -440,24 +436,25 @@ __device__ __forceinline__ u32 opp_before(const Ch& ch, u32 pos) {
   typedef typename Ch::Word W;
   if (pos >= Ch::kWin) return ch.total;
   const u32 g = pos >> GroupShift<Ch::kG>::value, b = pos & (Ch::kG - 1);
-  const u32 prior = readlane(ch.excl, g);
-  return b ? prior + popcount(read_group(ch.O, g) & ((W(1) << b) - W(1))) : prior;
+  return readlane(ch.excl, g) + popcount(read_group(ch.O, g) & ~(~W(0) << b));  // the group's pairs below b
 }
 
 // First admissible run end of the current window at or after er (a byte
-// offset in the window, possibly >= kWin), or kWin if none.  Branch-free: the
-// word of group er/kG and the first run end of the next group holding one are
-// both read, and the right one is selected.
+// offset in the window, possibly >= kWin), or kWin if none: in the word of
+// group er/kG above er, else the first run end of the next group holding one
+// (emask & (~1 << ge) are the groups after ge, none after the last).
 template <class Ch>
 __device__ __forceinline__ u32 first_end(const Ch& ch, u32 er) {
   typedef typename Ch::Word W;
   constexpr u32 kWin = Ch::kWin, kG = Ch::kG;
-  const u32 ge = er < kWin ? er >> GroupShift<kG>::value : 63u;
-  const W word = er < kWin ? read_group(ch.E, ge) & (~W(0) << (er & (kG - 1))) : W(0);
-  const u64 later = (er < kWin && ge < 63) ? ch.emask & (~0ull << (ge + 1)) : 0ull;
-  const u32 g2 = later ? ctz64(later) : 63u;
-  const u32 f2 = readlane(ch.fe, g2);
-  return word ? ge * kG + lowest_bit(word) : (later ? g2 * kG + f2 : kWin);
+  if (er >= kWin) return kWin;
+  const u32 ge = er >> GroupShift<kG>::value;
+  const W word = read_group(ch.E, ge) & (~W(0) << (er & (kG - 1)));
+  if (word) return ge * kG + lowest_bit(word);
+  const u64 later = ch.emask & (~1ull << ge);
+  if (!later) return kWin;
+  const u32 g2 = ctz64(later);
+  return g2 * kG + readlane(ch.fe, g2);
 }
 
 // Position in the current window of the need-th opposing pair at or after
@@ -490,24 +487,17 @@ __device__ u64 next_cut(Ch& ch, u64 c) {
   u32 p = s + 1;                                                    // next pair (p-1, p) to examine
   u32 need = ch.trig;                                               // opposing pairs still to the trigger
   const u32 c32 = (u32)c;
-  // The run-end summary is asked (one place, so its code is inlined once)
-  // when the chunk starts inside a stretch already known to hold no run end
-  // (ask = 1, position: the earliest admissible run end), and after a whole
-  // window without a run end (ask = 2, position: the next window).  If no run
-  // end comes before the limit, the chunk ends there.
-  u32 ask = summary_known(ch) ? 1u : 0u;
-  u32 apos = s + ch.sl - 1;
   for (;;) {
     if (p >= lim) return c + lim;
     if constexpr (Ch::kSummary) {
-      if (ask) {
-        const u32 b = (u32)((c + apos) >> 10);
-        if (ask == 1 && b > (ch.sumk >> 1)) {
-          ch.sumk = 0;  // past the known stretch
-        } else if (no_end_before(ch, b, c + lim)) {
-          return c + lim;
-        }
-        ask = 0;
+      // The last window entered held no run end (a stretch without run ends,
+      // at the start of a chunk or when the scan leaves such a window): the
+      // run-end summary tells whether any run end comes before the limit,
+      // from the earliest admissible one on; if none, the chunk ends there.
+      // Random data never asks.  One place, so its code is inlined once.
+      if (ch.emask == 0 && ch.cur != kNone) {
+        const u32 e_lo = s + ch.sl - 1;
+        if (no_end_before(ch, (u32)((c + (e_lo > p ? e_lo : p)) >> 10), c + lim)) return c + lim;
       }
     }
     const u32 sub = (u32)((c + p) / kWin);
@@ -537,10 +527,6 @@ __device__ u64 next_cut(Ch& ch, u64 c) {
       need -= left;  // no event in this window
       p = w + kWin;
       if (p >= lim) return c + lim;
-      if (Ch::kSummary && ch.emask == 0) {  // random data never gets here
-        ask = 2;
-        apos = p;
-      }
       break;
     }
   }
