@@ -303,54 +303,64 @@ __global__ __launch_bounds__(256) void insert_kernel(const DedupFile* __restrict
   owner[slot] = kNoOwner;  // unreachable: the table has more entries than chunks
 }
 
-// Pass 3: one wave per chunk.  A chunk with no owner is unique; a chunk with
-// an owner is a duplicate if the two have the same length and bytes (checked
-// 16 bytes per lane at a time).  The bytes of the unique chunks and of all
-// chunks are added up per workgroup, then into the totals.
+// Pass 3: one wave per 64 slots.  Each lane looks up its slot's chunk and
+// the chunk that owns its fingerprint (so the dependent lookups of 64 slots
+// run together); a chunk with no owner is unique, and a chunk whose owner has
+// another length is unique.  The wave then compares each remaining candidate
+// with its owner byte for byte, 4 KiB at a time (each lane 4 x 16 bytes of
+// both, all loads in flight together): a candidate is a duplicate only if all
+// bytes are equal.  The bytes of the unique chunks and of all chunks are
+// summed over the wave, then into the totals.
 __global__ __launch_bounds__(256) void verify_kernel(const DedupFile* __restrict__ files, u32 nfiles,
                                                      const u64* __restrict__ cuts, u64 nslots,
                                                      const u32* __restrict__ owner, u64* totals) {
-  __shared__ u64 s_orig[kWavesPerGroup], s_uniq[kWavesPerGroup];
   const u32 lane = lane_id();
-  const u32 wv = threadIdx.x >> 6;
-  const u64 slot = (u64)blockIdx.x * kWavesPerGroup + __builtin_amdgcn_readfirstlane(wv);
-  u64 orig = 0, uniq = 0;
+  const u64 slot = ((u64)blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6)) * 64 + lane;
+  u64 orig = 0, uniq = 0, len = 0;
+  const uint8_t* pa = nullptr;
+  const uint8_t* pb = nullptr;
+  bool cand = false;
   const uint8_t* data;
   u64 start, end;
   if (slot < nslots && chunk_of(files, nfiles, cuts, slot, data, start, end)) {
-    const u64 len = end - start;
+    len = end - start;
     orig = len;
+    uniq = len;
+    pa = data + start;
     const u32 o = owner[slot];
-    bool dup = false;
     if (o != kNoOwner) {
       const uint8_t* odata;
       u64 ostart, oend;
       chunk_of(files, nfiles, cuts, o, odata, ostart, oend);
-      dup = oend - ostart == len;
-      const uint8_t* pa = data + start;
-      const uint8_t* pb = odata + ostart;
-      for (u64 base = 0; dup && base < len; base += 1024) {
-        const u64 off = base + 16ull * lane;
-        u32 va[4], vb[4];
-        load16_chunk(pa, len, off, va);
-        load16_chunk(pb, len, off, vb);
-        const bool eq = va[0] == vb[0] && va[1] == vb[1] && va[2] == vb[2] && va[3] == vb[3];
-        dup = ballot(!eq) == 0;
+      cand = oend - ostart == len;
+      pb = odata + ostart;
+    }
+  }
+  // the candidates, one after another over the whole wave
+  for (u64 m = ballot(cand); m; m &= m - 1) {
+    const u32 l = ctz64(m);
+    const u64 n = readlane64(len, l);
+    const uint8_t* a = (const uint8_t*)readlane64((u64)pa, l);
+    const uint8_t* b = (const uint8_t*)readlane64((u64)pb, l);
+    bool same = true;
+    for (u64 base = 0; same && base < n; base += 4096) {
+      u32 va[4][4], vb[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const u64 off = base + 1024ull * u + 16ull * lane;
+        load16_chunk(a, n, off, va[u]);
+        load16_chunk(b, n, off, vb[u]);
       }
+      bool eq = true;
+#pragma unroll
+      for (int u = 0; u < 4; u++)
+        eq = eq && va[u][0] == vb[u][0] && va[u][1] == vb[u][1] && va[u][2] == vb[u][2] && va[u][3] == vb[u][3];
+      same = ballot(!eq) == 0;
     }
-    uniq = dup ? 0 : len;
+    if (same && lane == l) uniq = 0;
   }
-  if (lane == 0) {
-    s_orig[wv] = orig;
-    s_uniq[wv] = uniq;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    u64 so = 0, su = 0;
-    for (u32 i = 0; i < kWavesPerGroup; i++) {
-      so += s_orig[i];
-      su += s_uniq[i];
-    }
+  const u64 so = wave_incl_scan64(orig), su = wave_incl_scan64(uniq);  // lane 63 holds the wave's sums
+  if (lane == 63) {
     if (so) atomicAdd((unsigned long long*)&totals[0], (unsigned long long)so);
     if (su) atomicAdd((unsigned long long*)&totals[1], (unsigned long long)su);
   }
@@ -432,7 +442,8 @@ extern "C" int seqcdc_dedup_batch(seqcdc_plan* plan, const seqcdc_file* h_files,
                        (unsigned long long*)(totals + 2));
     hipLaunchKernelGGL(insert_kernel, dim3(grid), dim3(256), 0, st, d_files, nfiles, cuts, nslots,
                        (const u32*)digests, table, cap - 1, owner);
-    hipLaunchKernelGGL(verify_kernel, dim3((u32)((nslots + kWavesPerGroup - 1) / kWavesPerGroup)), dim3(256), 0, st,
+    hipLaunchKernelGGL(verify_kernel, dim3((u32)((nslots + 64 * kWavesPerGroup - 1) / (64 * kWavesPerGroup))), dim3(256),
+                       0, st,
                        d_files, nfiles, cuts, nslots, (const u32*)owner, totals);
     e = hipGetLastError();
   }
