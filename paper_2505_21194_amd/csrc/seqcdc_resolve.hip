@@ -29,11 +29,11 @@
 //    cross regions with no run end (zero runs, most short periodic patterns)
 //    without reading their bits: with no run end before the limit, the chunk
 //    ends at the limit whatever the opposing pairs do.
-//  - direct (DirectChain, skip-aware): 4 KiB of raw input bytes, one 64-byte
+//  - direct (DirectChain, skip-aware): 1 KiB of raw input bytes, one 16-byte
 //    group per lane, whose bits the chain computes itself when it enters the
 //    window.  There is no mark pass: only the windows a chain scans are read
-//    from HBM, so whole windows in the sub-minimum region after each cut and
-//    under skips are never loaded (Sec. III-B, III-C).
+//    from HBM, so the sub-minimum region after each cut and the bytes a skip
+//    passes over are never loaded (Sec. III-B, III-C).
 
 #include <hip/hip_runtime.h>
 
@@ -249,38 +249,43 @@ __device__ __forceinline__ bool no_end_before(MarkedChain& ch, u32 b, u64 L) {
 }
 
 // ---------------------------------------------------------------------------
-// The direct (skip-aware) chain: raw 4 KiB windows, bits computed on entry
+// The direct (skip-aware) chain: raw 1 KiB windows, bits computed on entry
 // ---------------------------------------------------------------------------
 
-constexpr u32 kRawRing = 4;          // LDS window slots per wave: window w lives in slot w % kRawRing
-constexpr u32 kRawSlotChunks = 258;  // aligned 16-byte chunks per slot
+constexpr u32 kDirectWin = 1024;                 // input bytes per window: 64 lanes x 16
+constexpr u32 kDirectSlots = 8;                  // LDS window slots per wave
+constexpr u32 kDirectSlotChunks = 66;            // aligned 16-byte chunks per slot
+constexpr u32 kDirectLdsChunks = kDirectSlots * kDirectSlotChunks;
 
-// The slot of window w holds the aligned 16-byte chunks 256w - 1 .. 256w + 256
-// of the file (counted from the aligned address at or below its first byte):
-// the window's 4 KiB wherever it starts within a chunk, and the 16 bytes
-// before it.  Chunks outside the file are clamped to its first or last chunk
-// (always in bounds: an aligned chunk never straddles a page); bytes outside
-// the file are masked when the bits are computed.  The lanes hold the
-// window's bits as the marked chain does (lane l: bytes 64l .. 64l + 63), so
-// the same scan steps run over them.
+// Slots hold the aligned 16-byte chunks 64w - 1 .. 64w + 64 of window w
+// (counted from the aligned address at or below the file's first byte): the
+// window's 1 KiB wherever it starts within a chunk, plus the 16 bytes before
+// it (the predecessors of lane 0's bytes).  Any slot holds any window; lane
+// i < kDirectSlots of `tag` names the window in slot i.  Windows are entered
+// in increasing order, so a slot holding a window below the current one is
+// free.  No fetch is ever issued into a slot whose earlier fetch may still be
+// in flight: prefetches are issued right after a wait for all earlier ones,
+// into slots that were free then; a window that was not prefetched goes into
+// the current window's slot, whose fetch completed before it was read; and a
+// new chain first waits for the fetches its wave left in flight.
 struct DirectChain {
-  static constexpr u32 kWin = kSubBytes;
-  static constexpr u32 kG = 64;
+  static constexpr u32 kWin = kDirectWin;
+  static constexpr u32 kG = 16;
   static constexpr bool kSummary = false;
-  typedef u64 Word;
+  typedef u32 Word;
   const uint8_t* base;  // aligned address at or below the file's first byte
   u64 last_chunk;       // chunks 0 .. last_chunk overlap the file (n > 0)
   u64 n;
-  u32 groups;           // ceil(n / 64)
-  u32 r;                // the first byte's offset in its chunk (0..15)
+  u32 nwin;             // ceil(n / 1024)
+  u32 r;                // first byte's offset in its chunk (0..15)
   u32 down_is_fav;      // decreasing mode
   u32 flip;             // 0x80808080 for signed bytes (x ^ 0x80 orders as the signed value), else 0
   u32 min_size, max_size, sl, trig, skip;
   u32 cur;              // window whose bits are held (kNone = none)
-  u32 pf_base;          // bit i of pf_mask: the DMA of window pf_base + i into its slot was issued
-  u32 pf_mask;
-  SEQCDC_LOCAL u32x4* win;  // kRawRing slots of kRawSlotChunks chunks
-  u64 E, O;             // lane l: bytes 64l .. 64l + 63 of the window
+  u32 cur_slot;         // its slot
+  u32 tag;              // lane i < kDirectSlots: window held by slot i (kNone = empty)
+  SEQCDC_LOCAL u32x4* win;  // kDirectSlots slots of kDirectSlotChunks chunks
+  u32 E, O;             // lane l: bits of bytes 16l .. 16l+15 of the window (16 each)
   u32 incl, excl, fe, total;
   u64 emask;
 };
@@ -291,7 +296,7 @@ __device__ __forceinline__ void chain_init(DirectChain& ch, const FileDesc& F, S
   ch.base = (const uint8_t*)(addr - ch.r);
   ch.n = F.n;
   ch.last_chunk = F.n ? (ch.r + F.n - 1) >> 4 : 0;
-  ch.groups = (u32)((F.n + 63) >> 6);
+  ch.nwin = (u32)((F.n + kDirectWin - 1) / kDirectWin);
   ch.down_is_fav = F.mode & 1;
   ch.flip = (F.mode & 2) ? 0x80808080u : 0u;
   ch.min_size = (u32)F.min_size;
@@ -300,109 +305,111 @@ __device__ __forceinline__ void chain_init(DirectChain& ch, const FileDesc& F, S
   ch.trig = F.trig;
   ch.skip = F.skip;
   ch.cur = kNone;
-  ch.pf_base = 0;
-  ch.pf_mask = 0;
+  ch.cur_slot = 0;
+  ch.tag = kNone;
   ch.win = win;
   SEQCDC_WAIT_VMEM();  // fetches of the wave's previous chain
   ch.E = ch.O = 0;
   ch.incl = ch.excl = ch.total = 0;
-  ch.fe = 64;
+  ch.fe = 16;
   ch.emask = 0;
 }
 
-// Starts the DMA of window w into its slot: slot chunk j is aligned chunk
-// 256w - 1 + j, lane l copying slot chunks l, 64 + l, 128 + l, 192 + l, and
-// lanes 0 and 1 slot chunks 256 and 257.
-__device__ __forceinline__ void dma_window(const DirectChain& ch, u32 w) {
+// Starts the DMA of window w into slot s: lane l copies chunk 64w - 1 + l into
+// slot chunk l, lanes 0 and 1 chunks 64w + 63 and 64w + 64 into slot chunks 64
+// and 65.  Chunks outside the file are clamped to its first or last chunk
+// (always in bounds: a 16-byte aligned chunk never straddles a page); bytes
+// outside the file are masked when the bits are computed.
+__device__ __forceinline__ void dma_raw(const DirectChain& ch, u32 w, u32 s) {
   const u32 lane = lane_id();
-  SEQCDC_LOCAL u32x4* dst = ch.win + (w & (kRawRing - 1)) * kRawSlotChunks;
-  const u64 first = (u64)w * 256;  // aligned chunk of slot chunk 1
-#pragma unroll
-  for (u32 k = 0; k < 4; k++) {
-    const u64 g = first + 64 * k + lane;  // slot chunk 64k + lane is aligned chunk g - 1
-    const u64 gm = g == 0 ? 0 : (g - 1 < ch.last_chunk ? g - 1 : ch.last_chunk);
-    __builtin_amdgcn_global_load_lds(as_global((const void*)(ch.base + 16 * gm)), dst + 64 * k, 16, 0, 0);
-  }
+  SEQCDC_LOCAL u32x4* dst = ch.win + s * kDirectSlotChunks;
+  const u64 first = (u64)w * 64;  // chunk index of the window's slot chunk 1
+  const u64 g = first + lane;     // slot chunk `lane` is chunk g - 1
+  const u64 gm = g == 0 ? 0 : (g - 1 < ch.last_chunk ? g - 1 : ch.last_chunk);
+  __builtin_amdgcn_global_load_lds(as_global((const void*)(ch.base + 16 * gm)), dst, 16, 0, 0);
   if (lane < 2) {
-    const u64 t = first + 255 + lane;
+    const u64 t = first + 63 + lane;
     const u64 tm = t < ch.last_chunk ? t : ch.last_chunk;
-    __builtin_amdgcn_global_load_lds(as_global((const void*)(ch.base + 16 * tm)), dst + 256, 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(as_global((const void*)(ch.base + 16 * tm)), dst + 64, 16, 0, 0);
   }
 }
 
-// Enters window `sub` and computes its bits and per-window facts (Sec. III-D:
-// favourable and opposing pairs, then run ends of SeqLength bytes).  The
-// windows the chain is likely to need next are fetched as the marked chain
-// fetches them: the next one and the two from `hint` on, only among the
-// kRawRing - 1 windows after `sub` (their slots never collide).  Each lane
-// reads its 64 bytes and the 16 before them, so its first byte's predecessor
-// and the favourable pairs before it come from its own reads.
-__device__ __forceinline__ void ensure(DirectChain& ch, u32 sub, u32 hint) {
-  if (ch.cur == sub) return;
+// Slot holding window w, or kNone.
+__device__ __forceinline__ u32 slot_of(const DirectChain& ch, u32 w) {
+  const u64 m = ballot(lane_id() < kDirectSlots && ch.tag == w);
+  return m ? ctz64(m) : kNone;
+}
+
+// Starts fetching window w into a free slot if it is in the file, not held
+// and a slot is free (never the slot of window `keep`).
+__device__ __forceinline__ void prefetch_raw(DirectChain& ch, u32 w, u32 keep) {
+  if (w >= ch.nwin) return;
   const u32 lane = lane_id();
-  const u32 d = sub - ch.pf_base;
-  u32 mask = d < kRawRing ? ch.pf_mask >> d : 0u;
-  if (!(mask & 1u)) dma_window(ch, sub);
+  const u64 held = ballot(lane < kDirectSlots && ch.tag == w);
+  const u64 free = ballot(lane < kDirectSlots && (ch.tag == kNone || ch.tag < keep));
+  if (held || !free) return;
+  const u32 s = ctz64(free);
+  dma_raw(ch, w, s);
+  if (lane == s) ch.tag = w;
+}
+
+// Loads window w and computes its bits and per-window facts.  On entry the
+// fetches of the windows the chain is likely to need next are started: the
+// next one (the scan continues) and the two from `hint` on, the window where
+// the scan would restart if a cut were found right at the current position (a
+// cut is usually a few hundred bytes away, and the scan after it starts
+// min_size - SeqLength bytes later).
+__device__ __forceinline__ void ensure(DirectChain& ch, u32 w, u32 hint) {
+  if (ch.cur == w) return;
+  const u32 lane = lane_id();
+  u32 s = slot_of(ch, w);
+  if (s == kNone) {  // not prefetched: into the slot of the window entered before (slot 0 in a new chain)
+    s = ch.cur_slot;
+    dma_raw(ch, w, s);
+    if (lane == s) ch.tag = w;
+  }
+  ch.cur_slot = s;
   SEQCDC_WAIT_VMEM();
-  // slot bytes r + 64l - 16 + 16 .. : file bytes 4096 sub + 64l - 16 .. 4096 sub + 64l + 63
-  const SEQCDC_LOCAL u32* sw = (const SEQCDC_LOCAL u32*)(ch.win + (sub & (kRawRing - 1)) * kRawSlotChunks);
-  const u32 d0 = (ch.r + 64 * lane) >> 2, sh = ch.r & 3;
-  u32 dw[21];
+  // lane l's 16 bytes and the 16 before them: slot bytes r + 16l .. r + 16l + 31,
+  // read as 9 aligned dwords and realigned
+  const SEQCDC_LOCAL u32* sw = (const SEQCDC_LOCAL u32*)(ch.win + s * kDirectSlotChunks);
+  const u32 d0 = (ch.r + 16 * lane) >> 2, sh = ch.r & 3;
+  u32 dw[9];
 #pragma unroll
-  for (int k = 0; k < 21; k++) dw[k] = sw[d0 + k];
-  mask |= 1u;
-  u32 want = 2u;  // the next window, hint and hint+1, inside the stream
-  const u32 hi = hint - sub;  // hint >= sub
-  if (hi < kRawRing - 1) want |= 3u << hi;
-  const u32 nwin = (ch.groups + 63) >> 6;
-  const u32 room = nwin > sub ? nwin - sub : 0u;
-  if (room < kRawRing) want &= (1u << room) - 1u;
-  want &= (1u << kRawRing) - 1u;
-  want &= ~mask;
-  mask |= want;
-  while (want) {
-    dma_window(ch, sub + (u32)__builtin_ctz(want));
-    want &= want - 1u;
+  for (int k = 0; k < 9; k++) dw[k] = sw[d0 + k];
+  u32 halo[4], x[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    halo[k] = __builtin_amdgcn_alignbyte(dw[k + 1], dw[k], sh) ^ ch.flip;
+    x[k] = __builtin_amdgcn_alignbyte(dw[k + 5], dw[k + 4], sh) ^ ch.flip;
   }
-  ch.pf_base = sub;
-  ch.pf_mask = mask;
-  u32 x[20];
-#pragma unroll
-  for (int k = 0; k < 20; k++) x[k] = __builtin_amdgcn_alignbyte(dw[k + 1], dw[k], sh) ^ ch.flip;
-  const u64 q0 = (u64)sub * kSubBytes + 64 * lane;  // file offset of the lane's first byte
-  // the 16 bytes before: their favourable pairs (bit 0, whose predecessor is
-  // unknown, is never used for SeqLength <= 16) and their last byte
-  u32 hup, hdn;
-  compare16(&x[0], 0u, hup, hdn);
-  u32 prev_fav = ch.down_is_fav ? hdn : hup;
-  u32 prev_byte = x[3] >> 24;
-  u64 E = 0, O = 0;
-#pragma unroll
-  for (int j = 0; j < 4; j++) {
-    u32 up, dn;
-    compare16(&x[4 + 4 * j], prev_byte, up, dn);
-    u32 fav = ch.down_is_fav ? dn : up;
-    u32 opp = ch.down_is_fav ? up : dn;
-    if (j == 0 && q0 == 0) {  // byte 0 has no predecessor, and nothing comes before it
-      fav &= ~1u;
-      opp &= ~1u;
-      prev_fav = 0;
-    }
-    E |= (u64)run_ends16(fav, prev_fav, ch.sl - 1) << (16 * j);
-    O |= (u64)opp << (16 * j);
-    prev_fav = fav;
-    prev_byte = x[4 + 4 * j + 3] >> 24;
+  // the next fetches go to other slots while the bits are computed
+  prefetch_raw(ch, w + 1, w);
+  prefetch_raw(ch, hint, w);
+  prefetch_raw(ch, hint + 1, w);
+  // Sec. III-D: favourable / opposing pairs, then run ends of SeqLength bytes
+  u32 up, dn, hup, hdn;
+  compare16(x, halo[3] >> 24, up, dn);
+  compare16(halo, 0u, hup, hdn);  // only bits 2..15 are used (for lane 0's runs)
+  u32 fav = ch.down_is_fav ? dn : up;
+  u32 opp = ch.down_is_fav ? up : dn;
+  const u32 hfav = readlane(ch.down_is_fav ? hdn : hup, 0);
+  const u64 q0 = (u64)w * kDirectWin + 16 * lane;
+  if (q0 == 0) {  // byte 0 has no predecessor
+    fav &= ~1u;
+    opp &= ~1u;
   }
-  u64 keep = ~0ull;  // bytes of the file
+  u32 keep = 0xFFFFu;  // bytes of the file
   if (q0 >= ch.n) keep = 0;
-  else if (ch.n - q0 < 64) keep = (1ull << (u32)(ch.n - q0)) - 1ull;
-  ch.E = E & keep;
-  ch.O = O & keep;
-  ch.cur = sub;
-  ch.emask = ballot(ch.E != 0);
-  ch.fe = ch.E ? ctz64(ch.E) : 64u;
+  else if (ch.n - q0 < 16) keep = (1u << (u32)(ch.n - q0)) - 1u;
+  const u32 e = run_ends16(fav, shift_up_lanes(fav, hfav), ch.sl - 1) & keep;
+  ch.E = e;
+  ch.O = opp & keep;
+  ch.cur = w;
+  ch.emask = ballot(e != 0);
+  ch.fe = e ? (u32)__builtin_ctz(e) : 16u;
   if (skipping(ch)) {
-    const u32 cnt = (u32)__popcll(ch.O);
+    const u32 cnt = (u32)__popc(ch.O);
     ch.incl = wave_incl_scan(cnt);
     ch.excl = ch.incl - cnt;
     ch.total = readlane(ch.incl, 63);
@@ -410,14 +417,17 @@ __device__ __forceinline__ void ensure(DirectChain& ch, u32 sub, u32 hint) {
 }
 
 // Group words: one lane's E or O bits.
+__device__ __forceinline__ u32 read_group(u32 v, u32 g) { return readlane(v, g); }
 __device__ __forceinline__ u64 read_group(u64 v, u32 g) { return readlane64(v, g); }
+__device__ __forceinline__ u32 popcount(u32 v) { return (u32)__popc(v); }
 __device__ __forceinline__ u32 popcount(u64 v) { return (u32)__popcll(v); }
+__device__ __forceinline__ u32 lowest_bit(u32 v) { return (u32)__builtin_ctz(v); }
 __device__ __forceinline__ u32 lowest_bit(u64 v) { return ctz64(v); }
 
 template <u32 G>
 struct GroupShift {
-  static constexpr u32 value = G == 64 ? 6 : 0;
-  static_assert(value != 0, "groups are 64 bytes");
+  static constexpr u32 value = G == 64 ? 6 : G == 16 ? 4 : 0;
+  static_assert(value != 0, "groups are 16 or 64 bytes");
 };
 
 // Opposing pairs of the window at positions < pos (0 <= pos <= kWin).
@@ -686,7 +696,7 @@ struct WaveLds<MarkedChain> {
 };
 template <>
 struct WaveLds<DirectChain> {
-  static constexpr u32 kChunks = kRawRing * kRawSlotChunks;
+  static constexpr u32 kChunks = kDirectLdsChunks;
 };
 
 template <class Ch>
