@@ -166,10 +166,13 @@ TuneKey plan_key(const Plan* pl, const seqcdc_params* p) {
 // lengthen the continuations.
 u64 Plan::segment_for(u64 n, const seqcdc_params* p, bool single) const {
   u64 seg = seg_override;
-  if (!seg) {
-    TuneEntry te;
-    if (tune_lookup(plan_key(this, p), &te)) seg = te.seg_mult * p->min_size;
-    else seg = 128 * p->min_size;
+  TuneEntry te;
+  if (!seg && tune_lookup(plan_key(this, p), &te)) {
+    seg = te.seg_mult * p->min_size;  // the autotuner measured this length: used as it is
+  } else if (!seg) {
+    // untuned: a single stream's segments shrink until the chains fill the
+    // device once (cus x waves), never below 64 KiB x (min_size / 4 KiB)^2
+    seg = 128 * p->min_size;
     const u64 fill = n / ((u64)cus * waves_for(p));
     const u64 m = p->min_size >> 12;  // min_size in 4 KiB
     const u64 floor = m > 1 ? (64 * 1024) * std::min<u64>(m * m, 1u << 20) : 64 * 1024;
