@@ -83,10 +83,11 @@ int seqcdc_plan_destroy(seqcdc_plan* plan);
 
 /* Tuning knobs of a plan (0 = keep).  segment_bytes: length of the segments
  * a stream is split into for speculative resolution (rounded up to a whole
- * number of mark spans; default: the autotuner's choice, used as it is, else
- * 128 x min_size, which a call on a single stream shortens down to the
- * stream's bytes divided by the device's chain waves (CUs x waves_per_cu),
- * but not below 64 KiB x (min_size / 4 KiB)^2; at least 64 KiB);
+ * number of mark spans; default: the autotuner's choice, used as it is on
+ * streams of at least half the size it was measured on, else 128 x min_size;
+ * on other single streams it shrinks down to the stream's bytes divided by
+ * the device's chain waves (CUs x waves_per_cu), but not below
+ * 64 KiB x (min_size / 4 KiB)^2; at least 64 KiB);
  * mark_span_blocks: 1 KiB blocks per mark span, the
  * unit of marking work (4, 8, 16, 32 or 64); waves_per_cu: waves per compute
  * unit of the persistent chain kernels, one chain per wave (4..32, a

@@ -166,17 +166,20 @@ TuneKey plan_key(const Plan* pl, const seqcdc_params* p) {
 // lengthen the continuations.
 u64 Plan::segment_for(u64 n, const seqcdc_params* p, bool single) const {
   u64 seg = seg_override;
-  TuneEntry te;
-  if (!seg && tune_lookup(plan_key(this, p), &te)) {
-    seg = te.seg_mult * p->min_size;  // the autotuner measured this length: used as it is
-  } else if (!seg) {
-    // untuned: a single stream's segments shrink until the chains fill the
-    // device once (cus x waves), never below 64 KiB x (min_size / 4 KiB)^2
-    seg = 128 * p->min_size;
-    const u64 fill = n / ((u64)cus * waves_for(p));
-    const u64 m = p->min_size >> 12;  // min_size in 4 KiB
-    const u64 floor = m > 1 ? (64 * 1024) * std::min<u64>(m * m, 1u << 20) : 64 * 1024;
-    if (single && fill < seg) seg = std::max<u64>(fill, std::min<u64>(floor, seg));
+  if (!seg) {
+    // the autotuner's length is used as it is for streams of at least half
+    // the size it was measured on; otherwise (and untuned) a single stream's
+    // segments shrink until the chains fill the device once (cus x waves),
+    // never below 64 KiB x (min_size / 4 KiB)^2
+    TuneEntry te;
+    const bool tuned = tune_lookup(plan_key(this, p), &te);
+    seg = tuned ? te.seg_mult * p->min_size : 128 * p->min_size;
+    if (single && !(tuned && 2 * n >= te.sample)) {
+      const u64 fill = n / ((u64)cus * waves_for(p));
+      const u64 m = p->min_size >> 12;  // min_size in 4 KiB
+      const u64 floor = m > 1 ? (64 * 1024) * std::min<u64>(m * m, 1u << 20) : 64 * 1024;
+      if (fill < seg) seg = std::max<u64>(fill, std::min<u64>(floor, seg));
+    }
   }
   seg = std::max<u64>(seg, 64 * 1024);
   if (n / seg > kMaxSegments) seg = n / kMaxSegments + 1;

@@ -86,6 +86,7 @@ extern "C" int seqcdc_autotune(seqcdc_plan* plan, const void* d_sample, uint64_t
   pl->mode = 0;
   TuneEntry best;
   best.key = plan_key(pl, p);
+  best.sample = n;
   best.ms = 1e30;
   auto trial = [&](u64 seg_mult, u32 span, u32 waves) -> int {
     pl->seg_override = seg_mult * p->min_size;

@@ -50,6 +50,7 @@ struct TuneEntry {
   u32 waves_per_cu = 8;
   int mode = 0;
   double ms = 0;
+  u64 sample = 0;  // bytes of the stream the choices were measured on
 };
 
 struct Plan {
