@@ -40,6 +40,12 @@ constexpr u32 kSha256H0[8] = {0x6a09e667u, 0xbb67ae85u, 0x3c6ef372u, 0xa54ff53au
                               0x510e527fu, 0x9b05688cu, 0x1f83d9abu, 0x5be0cd19u};
 
 __device__ __forceinline__ u32 rotr(u32 x, u32 n) { return __builtin_amdgcn_alignbit(x, x, n); }
+
+// Three-input bitwise functions as one v_bitop3 each: bit i of the 8-bit table
+// is the result for the input bits (x, y, z) = (i >> 2, (i >> 1) & 1, i & 1).
+__device__ __forceinline__ u32 xor3(u32 x, u32 y, u32 z) { return __builtin_amdgcn_bitop3_b32(x, y, z, 0x96); }
+__device__ __forceinline__ u32 choose(u32 x, u32 y, u32 z) { return __builtin_amdgcn_bitop3_b32(x, y, z, 0xCA); }
+__device__ __forceinline__ u32 majority(u32 x, u32 y, u32 z) { return __builtin_amdgcn_bitop3_b32(x, y, z, 0xE8); }
 __device__ __forceinline__ u32 bswap32(u32 x) { return __builtin_amdgcn_perm(0u, x, 0x00010203u); }
 
 // One 64-byte block into the state (FIPS 180-4 Sec. 6.2.2), the message
@@ -53,16 +59,16 @@ __device__ __forceinline__ void sha256_block(u32 st[8], u32 w[16]) {
       wi = w[i];
     } else {
       const u32 w15 = w[(i - 15) & 15], w2 = w[(i - 2) & 15];
-      const u32 s0 = rotr(w15, 7) ^ rotr(w15, 18) ^ (w15 >> 3);
-      const u32 s1 = rotr(w2, 17) ^ rotr(w2, 19) ^ (w2 >> 10);
+      const u32 s0 = xor3(rotr(w15, 7), rotr(w15, 18), w15 >> 3);  // sigma0 (Sec. 4.1.2)
+      const u32 s1 = xor3(rotr(w2, 17), rotr(w2, 19), w2 >> 10);   // sigma1
       wi = w[i & 15] + s0 + w[(i - 7) & 15] + s1;
       w[i & 15] = wi;
     }
-    const u32 S1 = rotr(e, 6) ^ rotr(e, 11) ^ rotr(e, 25);
-    const u32 ch = (e & f) ^ (~e & g);
+    const u32 S1 = xor3(rotr(e, 6), rotr(e, 11), rotr(e, 25));  // Sigma1 (Sec. 4.1.2)
+    const u32 ch = choose(e, f, g);                              // Ch: f where e is 1, g where e is 0
     const u32 t1 = h + S1 + ch + kSha256K[i] + wi;
-    const u32 S0 = rotr(a, 2) ^ rotr(a, 13) ^ rotr(a, 22);
-    const u32 maj = (a & b) ^ (a & c) ^ (b & c);
+    const u32 S0 = xor3(rotr(a, 2), rotr(a, 13), rotr(a, 22));  // Sigma0
+    const u32 maj = majority(a, b, c);                           // Maj
     const u32 t2 = S0 + maj;
     h = g;
     g = f;
@@ -83,19 +89,33 @@ __device__ __forceinline__ void sha256_block(u32 st[8], u32 w[16]) {
   st[7] += h;
 }
 
-// The 16 big-endian message words of the 64 bytes at p (p + 64 <= end), or
-// of the last part of a message: the bytes [p, end) followed, when `pad`, by
-// the 0x80 byte at end - p (< 64) and zeros; all zeros when p > end.  Only
-// aligned words that hold a byte below `end` are read: such a word never
-// crosses a page end.
-__device__ __forceinline__ void load_words(const uint8_t* p, const uint8_t* end, bool pad, u32 w[16]) {
+// The 17 aligned 32-bit words from the one at or below p (they cover the 64
+// bytes at p wherever p falls in a word).  Only words that hold a byte below
+// `end` are read from there (such a word never crosses a page end); the
+// others read the word at `safe`, a valid address: all their bytes lie at or
+// past `end`, where words_from_raw ignores them.  Every word is one load in
+// every lane, with no branch around it, so the loads of a block can be waited
+// for as one group.
+__device__ __forceinline__ void load_raw(const uint8_t* p, const uint8_t* end, const u32* safe, u32 d[17]) {
   const uintptr_t a = (uintptr_t)p;
   const u32 sh = (u32)(a & 3);
-  const SEQCDC_GLOBAL u32* base = as_global((const u32*)(a - sh));
   const uintptr_t e = (uintptr_t)end;
-  u32 d[17];
 #pragma unroll
-  for (int j = 0; j < 17; j++) d[j] = (a - sh + 4 * j < e) ? base[j] : 0u;
+  for (int j = 0; j < 17; j++) {
+    const uintptr_t wa = a - sh + 4 * j;
+    d[j] = *as_global(wa < e ? (const u32*)wa : safe);
+  }
+}
+
+// The 16 big-endian message words of the 64 bytes at p (p + 64 <= end), or
+// of the last part of a message: the bytes [p, end) followed, when `pad`, by
+// the 0x80 byte at end - p (< 64) and zeros; all zeros when p > end.  d holds
+// the words load_raw(p, end) read; their bytes at or past `end` are ignored.
+__device__ __forceinline__ void words_from_raw(const u32 d[17], const uint8_t* p, const uint8_t* end, bool pad,
+                                               u32 w[16]) {
+  const uintptr_t a = (uintptr_t)p;
+  const u32 sh = (u32)(a & 3);
+  const uintptr_t e = (uintptr_t)end;
   // message bytes from p: none when p is past the end (the aligned word read
   // first may still hold the message's last bytes; they are masked off)
   const bool inside = a <= e;
@@ -167,12 +187,13 @@ __device__ __forceinline__ bool chunk_of(const DedupFile* __restrict__ files, u3
 }
 
 // Block b of the padded message of the len bytes at p (FIPS 180-4 Sec.
-// 5.1.1): the message bytes, the 0x80 byte right after them, zeros, and the
-// 64-bit bit length in the last 8 bytes of the last of the nb blocks.  The
-// same code serves every block (load_words reads nothing at or past the end
-// and puts the 0x80 byte where the message ends inside the block).
-__device__ __forceinline__ void padded_block(const uint8_t* p, u64 len, u64 b, u64 nb, u32 w[16]) {
-  load_words(p + 64 * b, p + len, true, w);
+// 5.1.1) from the words load_raw(p + 64 b, p + len) read: the message bytes,
+// the 0x80 byte right after them, zeros, and the 64-bit bit length in the last
+// 8 bytes of the last of the nb blocks.  The same code serves every block
+// (nothing at or past the end was read, and the 0x80 byte goes where the
+// message ends inside the block).
+__device__ __forceinline__ void padded_block(const u32 d[17], const uint8_t* p, u64 len, u64 b, u64 nb, u32 w[16]) {
+  words_from_raw(d, p + 64 * b, p + len, true, w);
   if (b + 1 == nb) {
     w[14] = (u32)((len * 8) >> 32);
     w[15] = (u32)(len * 8);
@@ -184,25 +205,42 @@ __device__ __forceinline__ void padded_block(const uint8_t* p, u64 len, u64 b, u
 // wave stay busy however the chunk lengths of neighbouring slots differ.  A
 // wave takes slots from the global queue kBatch at a time (every lane
 // executes that atomic, lane 0 adding kBatch, in wave-uniform control flow)
-// and hands them to its idle lanes in lane order (ranks by mbcnt).  Slots past
-// a file's count get a zero digest.  A wave ends once the queue is empty and
-// its lanes have finished: every step either hashes a block or takes slots.
+// and hands them in lane order (ranks by mbcnt) to the lanes that need a
+// message after the current step: idle lanes, and lanes hashing the last
+// block of theirs.  The words of the block a lane hashes at the next step (its
+// message's next block, or the first block of the message it takes up next)
+// are loaded during the current step, so the loads run while the current
+// block's 64 rounds do.  A lane that was idle hashes an empty block for one
+// step while its first block loads.  Slots past a file's count get a zero
+// digest.  A wave ends once the queue is empty and its lanes have finished:
+// every step either hashes a block or takes slots.
 constexpr u32 kShaBatch = 64;
 
 __global__ __launch_bounds__(256) void sha_queue_kernel(const DedupFile* __restrict__ files, u32 nfiles,
                                                         const u64* __restrict__ cuts, u64 nslots, u32* digests,
                                                         unsigned long long* next) {
+  const u32* safe = (const u32*)cuts;  // a valid word for the loads that read nothing
   u64 wb = 0, we = 0;      // wave-uniform: the wave's batch of slots [wb, we)
   bool exhausted = false;  // wave-uniform: the queue had no slot left
+  // the lane's current message: block b of nb is hashed at the next step
   u64 slot = 0;
   const uint8_t* p = nullptr;
   u64 len = 0, b = 0, nb = 1;
   bool busy = false;
+  // the message the lane takes up after the current one
+  u64 nslot = 0;
+  const uint8_t* np = nullptr;
+  u64 nlen = 0;
+  bool has_next = false;
   u32 st[8];
 #pragma unroll
   for (int i = 0; i < 8; i++) st[i] = 0;
+  u32 dc[17];  // the words of block b, loaded during the previous step
+#pragma unroll
+  for (int j = 0; j < 17; j++) dc[j] = 0;
   for (;;) {
-    const u64 need = ballot(!busy);
+    const bool want = !has_next && (!busy || b + 1 == nb);
+    const u64 need = ballot(want);
     if (need && !exhausted) {
       if (wb == we) {
         const unsigned long long v = atomicAdd(next, lane_id() == 0 ? (unsigned long long)kShaBatch : 0ull);
@@ -213,21 +251,18 @@ __global__ __launch_bounds__(256) void sha_queue_kernel(const DedupFile* __restr
       if (!exhausted) {
         const u64 avail = we - wb;
         const u32 rank = __builtin_amdgcn_mbcnt_hi((u32)(need >> 32), __builtin_amdgcn_mbcnt_lo((u32)need, 0u));
-        if (!busy && rank < avail) {
-          slot = wb + rank;
-          if (slot < nslots) {
+        if (want && rank < avail) {
+          const u64 sl = wb + rank;
+          if (sl < nslots) {
             const uint8_t* data;
             u64 start, end;
-            if (chunk_of(files, nfiles, cuts, slot, data, start, end)) {
-              p = data + start;
-              len = end - start;
-              b = 0;
-              nb = (len + 8) / 64 + 1;
-              busy = true;
-#pragma unroll
-              for (int i = 0; i < 8; i++) st[i] = kSha256H0[i];
+            if (chunk_of(files, nfiles, cuts, sl, data, start, end)) {
+              nslot = sl;
+              np = data + start;
+              nlen = end - start;
+              has_next = true;
             } else {  // past its file's count
-              uint4* dst = (uint4*)(digests + 8 * slot);
+              uint4* dst = (uint4*)(digests + 8 * sl);
               dst[0] = make_uint4(0, 0, 0, 0);
               dst[1] = make_uint4(0, 0, 0, 0);
             }
@@ -237,17 +272,34 @@ __global__ __launch_bounds__(256) void sha_queue_kernel(const DedupFile* __restr
         wb += k < avail ? k : avail;
       }
     }
-    if (!ballot(busy)) {
-      if (exhausted) break;  // no slot left and no lane busy
+    if (!ballot(busy || has_next)) {
+      if (exhausted) break;  // no slot left and no lane with a message
       continue;              // the slots taken were past their files' counts: take more
     }
-    // one block of every busy lane's message; idle lanes read nothing (empty message)
+    // the words of the block hashed at the next step, loaded while this one is hashed
+    u32 dn[17];
+    {
+      const bool more = busy && b + 1 < nb;
+      const uint8_t* q = more ? p + 64 * (b + 1) : has_next ? np : nullptr;
+      const uint8_t* qe = more ? p + len : has_next ? np + nlen : nullptr;
+      load_raw(q, qe, safe, dn);
+    }
+    // one block of every busy lane's message; the other lanes hash an empty message
     u32 w[16];
-    padded_block(busy ? p : nullptr, busy ? len : 0, busy ? b : 0, busy ? nb : 1, w);
+    padded_block(dc, busy ? p : nullptr, busy ? len : 0, busy ? b : 0, busy ? nb : 1, w);
     u32 s2[8];
 #pragma unroll
     for (int i = 0; i < 8; i++) s2[i] = st[i];
     sha256_block(s2, w);
+#pragma unroll
+    for (int j = 0; j < 17; j++) dc[j] = dn[j];
+    // the loads complete here: after the rounds (s2[0] depends on all of
+    // them), before the digest stores below (a wait placed after those stores
+    // would wait for them too: one counter covers loads and stores)
+    asm volatile("" : "+v"(dc[0]), "+v"(dc[1]), "+v"(dc[2]), "+v"(dc[3]), "+v"(dc[4]), "+v"(dc[5]), "+v"(dc[6]),
+                 "+v"(dc[7]), "+v"(dc[8]), "+v"(s2[0]) : : "memory");
+    asm volatile("" : "+v"(dc[9]), "+v"(dc[10]), "+v"(dc[11]), "+v"(dc[12]), "+v"(dc[13]), "+v"(dc[14]),
+                 "+v"(dc[15]), "+v"(dc[16]) : : "memory");
     if (busy) {
 #pragma unroll
       for (int i = 0; i < 8; i++) st[i] = s2[i];
@@ -258,6 +310,17 @@ __global__ __launch_bounds__(256) void sha_queue_kernel(const DedupFile* __restr
         dst[1] = make_uint4(st[4], st[5], st[6], st[7]);
         busy = false;
       }
+    }
+    if (!busy && has_next) {  // take up the next message: its first block is in dc
+      slot = nslot;
+      p = np;
+      len = nlen;
+      b = 0;
+      nb = (len + 8) / 64 + 1;
+      busy = true;
+      has_next = false;
+#pragma unroll
+      for (int i = 0; i < 8; i++) st[i] = kSha256H0[i];
     }
   }
 }
@@ -436,10 +499,10 @@ extern "C" int seqcdc_dedup_batch(seqcdc_plan* plan, const seqcdc_file* h_files,
     e = hipGetLastError();
   }
   if (e == hipSuccess && nslots) {
-    // two waves per SIMD (fewer for small calls): enough to cover the block
-    // loads, while each lane hashes enough chunks that the ones still running
-    // when the queue empties are a small part of the work (measured: one or
-    // four waves per SIMD were 13 % and 6 % slower on a 2.5 GiB series)
+    // two waves per SIMD (fewer for small calls): each lane hashes enough
+    // chunks that the ones still running when the queue empties are a small
+    // part of the work (measured on a 2.5 GiB series: one or three waves per
+    // SIMD were 10 % and 9 % slower)
     const u32 sha_groups = (u32)std::max<u64>(1, std::min<u64>((u64)pl->cus * 2, (nslots + 255) / 256));
     hipLaunchKernelGGL(sha_queue_kernel, dim3(sha_groups), dim3(256), 0, st, d_files, nfiles, cuts, nslots, digests,
                        (unsigned long long*)(totals + 2));
