@@ -135,26 +135,28 @@ __device__ __forceinline__ void words_from_raw(const u32 d[17], const uint8_t* p
   }
 }
 
-// The 16 bytes at p + off .. (fewer where the chunk [p, p + len) ends; the
-// rest is zero) as 4 little-endian words, read as aligned words that each hold
-// a byte of the chunk.
-__device__ __forceinline__ void load16_chunk(const uint8_t* p, u64 len, u64 off, u32 out[4]) {
-  const uintptr_t a = (uintptr_t)(p + off);
-  const u32 sh = (u32)(a & 3);
-  const SEQCDC_GLOBAL u32* base = as_global((const u32*)(a - sh));
-  const uintptr_t e = (uintptr_t)(p + len);
-  u32 d[5];
+// The 16 bytes from byte sh (0..15) of the 32 bytes lo:hi (little-endian).
+__device__ __forceinline__ void realign16(const uint4& lo, const uint4& hi, u32 sh, u32 out[4]) {
+  const u32 w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+  const u32 ws = sh >> 2, bs = sh & 3;
+  u32 t[5];
 #pragma unroll
-  for (int j = 0; j < 5; j++) d[j] = (a - sh + 4 * j < e) ? base[j] : 0u;
-  const u64 left = len > off ? len - off : 0;
-  const u32 valid = left < 16 ? (u32)left : 16u;
+  for (int k = 0; k < 5; k++) t[k] = ws == 0 ? w[k] : ws == 1 ? w[k + 1] : ws == 2 ? w[k + 2] : w[k + 3];
 #pragma unroll
-  for (int k = 0; k < 4; k++) {
-    u32 x = __builtin_amdgcn_alignbyte(d[k + 1], d[k], sh);
-    const u32 o = 4 * k;
-    if (o + 4 > valid) x = valid > o ? x & ((1u << (8 * (valid - o))) - 1u) : 0u;
-    out[k] = x;
-  }
+  for (int k = 0; k < 4; k++) out[k] = __builtin_amdgcn_alignbyte(t[k + 1], t[k], bs);
+}
+
+// The two aligned 16-byte vectors that hold the 16 bytes of the chunk
+// [p, p + n) at off .. off + 15 (off < n; a multiple of 16), where sh = p mod
+// 16: the vector holding p + off, and the next one only while it holds a byte
+// of the chunk (an aligned vector never crosses a page end; otherwise the
+// first is read twice).  realign16(lo, hi, sh) gives the 16 bytes (those at or
+// past n unspecified).
+__device__ __forceinline__ void chunk16_raw(const uint8_t* p, u64 n, u64 off, u32 sh, uint4& lo, uint4& hi) {
+  const uintptr_t al = (uintptr_t)(p + off) - sh;
+  const uintptr_t end = (uintptr_t)(p + n);
+  lo = load16((const void*)al);
+  hi = load16((const void*)(al + 16 < end ? al + 16 : al));
 }
 
 // A file of the call: its bytes, the range of its cut slots, its count.
@@ -371,8 +373,8 @@ __global__ __launch_bounds__(256) void insert_kernel(const DedupFile* __restrict
 // run together); a chunk with no owner is unique, and a chunk whose owner has
 // another length is unique.  The wave then compares each remaining candidate
 // with its owner byte for byte, 4 KiB at a time (each lane 4 x 16 bytes of
-// both, all loads in flight together): a candidate is a duplicate only if all
-// bytes are equal.  The bytes of the unique chunks and of all chunks are
+// both, read as aligned 16-byte vectors and realigned, all loads in flight
+// together): a candidate is a duplicate only if all bytes are equal.  The bytes of the unique chunks and of all chunks are
 // summed over the wave, then into the totals.
 __global__ __launch_bounds__(256) void verify_kernel(const DedupFile* __restrict__ files, u32 nfiles,
                                                      const u64* __restrict__ cuts, u64 nslots,
@@ -405,20 +407,34 @@ __global__ __launch_bounds__(256) void verify_kernel(const DedupFile* __restrict
     const u64 n = readlane64(len, l);
     const uint8_t* a = (const uint8_t*)readlane64((u64)pa, l);
     const uint8_t* b = (const uint8_t*)readlane64((u64)pb, l);
+    const u32 sha = (u32)((uintptr_t)a & 15), shb = (u32)((uintptr_t)b & 15);
     bool same = true;
     for (u64 base = 0; same && base < n; base += 4096) {
-      u32 va[4][4], vb[4][4];
+      uint4 alo[4], ahi[4], blo[4], bhi[4];
+      u32 valid[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {  // every load first, then the compares
+        const u64 off = base + 1024ull * u + 16ull * lane;
+        const bool in = off < n;
+        const u64 oc = in ? off : 0;  // lanes past the end read the chunk's first bytes and compare none
+        valid[u] = in ? (n - off < 16 ? (u32)(n - off) : 16u) : 0u;
+        chunk16_raw(a, n, oc, sha, alo[u], ahi[u]);
+        chunk16_raw(b, n, oc, shb, blo[u], bhi[u]);
+      }
+      u32 diff = 0;
 #pragma unroll
       for (int u = 0; u < 4; u++) {
-        const u64 off = base + 1024ull * u + 16ull * lane;
-        load16_chunk(a, n, off, va[u]);
-        load16_chunk(b, n, off, vb[u]);
-      }
-      bool eq = true;
+        u32 va[4], vb[4];
+        realign16(alo[u], ahi[u], sha, va);
+        realign16(blo[u], bhi[u], shb, vb);
 #pragma unroll
-      for (int u = 0; u < 4; u++)
-        eq = eq && va[u][0] == vb[u][0] && va[u][1] == vb[u][1] && va[u][2] == vb[u][2] && va[u][3] == vb[u][3];
-      same = ballot(!eq) == 0;
+        for (int k = 0; k < 4; k++) {
+          const u32 v = valid[u] > 4u * k ? valid[u] - 4u * k : 0u;  // bytes of word k that belong to the chunk
+          const u32 mask = v >= 4 ? ~0u : (1u << (8 * v)) - 1u;
+          diff |= (va[k] ^ vb[k]) & mask;
+        }
+      }
+      same = ballot(diff != 0) == 0;
     }
     if (same && lane == l) uniq = 0;
   }
