@@ -48,6 +48,17 @@ def test_autotune_keeps_results(env):
         assert ms > 0
         seg, span, waves = seq.seqcdc_plan_get_tuning(plan, d.numel(), p)
         assert seg > 0 and span in (4, 8, 16, 32, 64) and 0 < waves <= 32
+        # a stream of the tuned size uses the tuned segment length as measured (a candidate multiple of min_size)
+        assert seg % p.min_size == 0 and seg // p.min_size in (32, 64, 128, 256, 512, 1024)
+        # a stream under half the tuned size shrinks it to fill the device: the stream's bytes over the chain
+        # waves (CUs x waves per CU), but not below 64 KiB x (min_size / 4 KiB)^2, and at least 64 KiB
+        small = 4 << 20
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        m = p.min_size >> 12
+        floor = (64 << 10) * min(m * m, 1 << 20) if m > 1 else 64 << 10
+        fill = small // (cus * waves)
+        expect = max(fill, min(floor, seg)) if fill < seg else seg
+        assert seq.seqcdc_plan_get_tuning(plan, small, p)[0] == max(expect, 64 << 10)
         got = seq.chunk(d, p, plan=plan).cpu().numpy().astype(np.uint64)
         assert np.array_equal(got, want)
     finally:
