@@ -141,37 +141,43 @@ def batch_workload(seq, torch, dev):
     return buf, sizes, total, pb, cut_offs, bcuts, bcounts, files, ftab, otab
 
 
-def pipelined_batches(seq, torch, stream, plan, ftab, pb, otab, bcuts, bcounts, total, steps, warmup):
-    """The batch with two calls in flight: the given plan on `stream` and a second plan on a second stream (default
-    priority), each writing its own outputs, the calls alternating.  Rate = batches x bytes over the time of 2*steps
-    calls; both output sets are compared with the eager call's afterwards."""
+def pipelined_batches(seq, torch, stream, plan, ftab, pb, otab, bcuts, bcounts, total, steps, warmup, in_flight=3):
+    """The batch with `in_flight` calls in flight: the given plan on `stream` and further plans on streams of their
+    own (default priority), each tuned for the batch and writing its own outputs, the calls taking turns.  Rate =
+    batches x bytes over the time of in_flight*steps calls; every output set is compared with the eager call's
+    afterwards."""
     torch.cuda.synchronize()
     want_cuts, want_counts = bcuts.cpu().numpy(), bcounts.cpu().numpy()
-    side = torch.cuda.Stream()
-    plan2 = seq.seqcdc_plan_create()
-    cuts2, counts2 = torch.empty_like(bcuts), torch.empty_like(bcounts)
+    lanes = [(plan, stream, bcuts, bcounts)]
+    extra = []
     try:
-        seq.seqcdc_autotune_batch(plan2, ftab, [pb], cuts2.data_ptr(), otab, counts2.data_ptr(), stream=side)
+        for _ in range(in_flight - 1):
+            st = torch.cuda.Stream()
+            pl = seq.seqcdc_plan_create()
+            extra.append(pl)
+            c, n = torch.empty_like(bcuts), torch.empty_like(bcounts)
+            seq.seqcdc_autotune_batch(pl, ftab, [pb], c.data_ptr(), otab, n.data_ptr(), stream=st)
+            lanes.append((pl, st, c, n))
         torch.cuda.synchronize()
-        lanes = [(plan, stream, bcuts, bcounts), (plan2, side, cuts2, counts2)]
 
         def call(i):
-            pl, st, c, n = lanes[i & 1]
+            pl, st, c, n = lanes[i % in_flight]
             seq.seqcdc_chunk_batch(ftab, [pb], c.data_ptr(), otab, n.data_ptr(), stream=st, plan=pl)
-        for i in range(2 * warmup):
+        for i in range(in_flight * warmup):
             call(i)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for i in range(2 * steps):
+        for i in range(in_flight * steps):
             call(i)
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / (2 * steps)
+        dt = (time.perf_counter() - t0) / (in_flight * steps)
         same = all(bool(np.array_equal(c.cpu().numpy(), want_cuts) and np.array_equal(n.cpu().numpy(), want_counts))
                    for _, _, c, n in lanes)
     finally:
-        seq.seqcdc_plan_destroy(plan2)
+        for pl in extra:
+            seq.seqcdc_plan_destroy(pl)
     traffic = stored_step_traffic("batched")
-    out = {"in_flight": 2, "ms_per_batch": round(dt * 1e3, 3), "GBps": round(total / dt / 1e9, 1),
+    out = {"in_flight": in_flight, "ms_per_batch": round(dt * 1e3, 3), "GBps": round(total / dt / 1e9, 1),
            "outputs_match": same}
     if traffic:  # counter bytes of one batch step over the time per batch
         out["traffic_frac"] = round(traffic / dt / 1e9 / HBM_PEAK_GBS, 4)
@@ -215,8 +221,8 @@ def batched(seq, torch, stream, plan, steps, warmup, dev, tune):
         graph_same = bool(np.array_equal(bcounts.cpu().numpy(), counts))
     finally:
         seq.seqcdc_batch_destroy(gb)
-    # two batches in flight: a second plan (tuned the same way) on its own stream with its own outputs, the calls
-    # alternating between the two, so one batch's resolve overlaps the next one's marking
+    # three batches in flight: two more plans (tuned the same way) on streams of their own with their own outputs,
+    # the calls taking turns, so one batch's resolve overlaps the next ones' marking
     pipelined = pipelined_batches(seq, torch, stream, plan, ftab, pb, otab, bcuts, bcounts, total, steps, warmup)
     # one plain launch per file, the same files and parameters
     pcap = max(cut_offs[i + 1] - cut_offs[i] for i in range(nfiles))
@@ -695,12 +701,14 @@ def main():
     extra["plain_graph"] = {"ms_per_step": round(gdt * 1e3, 4), "GBps": round(n / gdt / 1e9, 1),
                             "counts_match": int(gcounts.item()) == count}
     log("plain as a prepared graph: %s" % extra["plain_graph"])
-    if not args.no_batch:
-        extra["batched"] = batched(seq, torch, stream, plan, args.steps, args.warmup, dev, not args.no_tune)
-        log("batched: %s" % extra["batched"])
+    # serving before the batched leg: the streams that leg's batches in flight take from torch's pool stay in
+    # the process, and with few hardware queues per process they can share one with a serving pass
     if not args.no_serve:
         extra["serving"] = serving(seq, torch, dev)
         log("serving: %s" % {k: v for k, v in extra["serving"].items() if k != "_checks"})
+    if not args.no_batch:
+        extra["batched"] = batched(seq, torch, stream, plan, args.steps, args.warmup, dev, not args.no_tune)
+        log("batched: %s" % extra["batched"])
     if not args.no_dedup:
         extra["dedup"] = dedup_leg(seq, torch, stream, args.steps, args.warmup, dev)
         log("dedup: %s" % {k: v for k, v in extra["dedup"].items() if k != "_check"})

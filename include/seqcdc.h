@@ -137,7 +137,8 @@ int seqcdc_plan_set_timing(seqcdc_plan* plan, int on);
 int seqcdc_plan_phase_ms(seqcdc_plan* plan, float* ms4);
 
 /* Autotuner: time candidate segment sizes, mark spans, resolve occupancies and
- * both resolve modes on the given device-resident sample stream, and keep
+ * both resolve modes on the given device-resident sample stream (the best of
+ * 3 calls each, then the 3 fastest again over 10 calls), and keep
  * the fastest in a process-wide cache keyed by (arch, CU count, seq_length,
  * average class), which plans consult for settings not set explicitly.
  * Results are exact for every choice; only speed differs.  *best_ms receives
@@ -180,7 +181,8 @@ int seqcdc_chunk_batch(seqcdc_plan* plan, const seqcdc_file* h_files, uint32_t n
 
 /* Autotuner for a batch: times candidate segment lengths (multiples of the
  * smallest min_size), mark spans, chain occupancies and both resolve modes on
- * seqcdc_chunk_batch itself with the given arguments (as for that call), and
+ * seqcdc_chunk_batch itself with the given arguments (as for that call; the
+ * best of 3 calls each, then the 3 fastest again over 10 calls), and
  * sets the fastest as the plan's own settings (those seqcdc_plan_set_tuning
  * and seqcdc_plan_set_mode set; they replace earlier ones and take precedence
  * over the process-wide cache).  The best settings for many files differ from

@@ -60,6 +60,25 @@ static int time_batch(Plan* pl, const seqcdc_file* files, u32 nfiles, const seqc
   return SEQCDC_OK;
 }
 
+// One timed setting of a search.  The searches time each candidate briefly,
+// then time the few fastest again for longer before choosing: a brief trial's
+// best call can be a lucky draw.
+struct Candidate {
+  u64 seg;  // segment multiple of min_size (one stream) or segment length in bytes (a batch)
+  u32 span, waves;
+  int mode;
+  double ms;
+};
+constexpr int kTrialReps = 3;   // timed calls per candidate in the search
+constexpr int kFinalReps = 10;  // timed calls per finalist
+constexpr size_t kFinalists = 3;
+
+std::vector<Candidate> finalists(std::vector<Candidate> c) {
+  std::sort(c.begin(), c.end(), [](const Candidate& a, const Candidate& b) { return a.ms < b.ms; });
+  if (c.size() > kFinalists) c.resize(kFinalists);
+  return c;
+}
+
 }  // namespace seqcdc
 
 using namespace seqcdc;
@@ -88,13 +107,15 @@ extern "C" int seqcdc_autotune(seqcdc_plan* plan, const void* d_sample, uint64_t
   best.key = plan_key(pl, p);
   best.sample = n;
   best.ms = 1e30;
+  std::vector<Candidate> tried;
   auto trial = [&](u64 seg_mult, u32 span, u32 waves) -> int {
     pl->seg_override = seg_mult * p->min_size;
     pl->span_override = span;
     pl->waves_override = waves;
     double ms = 0;
-    int r = time_config(pl, d_sample, n, p, d_cuts, cap, st, e0, e1, 3, &ms);
+    int r = time_config(pl, d_sample, n, p, d_cuts, cap, st, e0, e1, kTrialReps, &ms);
     if (r) return r;
+    tried.push_back(Candidate{seg_mult, span, waves, pl->mode, ms});
     if (ms < best.ms) {
       best.ms = ms;
       best.seg_mult = seg_mult;
@@ -128,6 +149,24 @@ extern "C" int seqcdc_autotune(seqcdc_plan* plan, const void* d_sample, uint64_t
       const u64 m = best.mode == 1 ? best.seg_mult : m0;
       for (u32 w : {8u, 16u})
         if ((rc = trial(m, s, w))) break;
+    }
+  }
+  if (!rc) {  // the fastest candidates again, each timed over more calls
+    best.ms = 1e30;
+    for (const Candidate& c : finalists(tried)) {
+      pl->mode = c.mode;
+      pl->seg_override = c.seg * p->min_size;
+      pl->span_override = c.span;
+      pl->waves_override = c.waves;
+      double ms = 0;
+      if ((rc = time_config(pl, d_sample, n, p, d_cuts, cap, st, e0, e1, kFinalReps, &ms))) break;
+      if (ms < best.ms) {
+        best.ms = ms;
+        best.seg_mult = c.seg;
+        best.span_blocks = c.span;
+        best.waves_per_cu = c.waves;
+        best.mode = c.mode;
+      }
     }
   }
   pl->mode = saved_mode;
@@ -169,14 +208,19 @@ extern "C" int seqcdc_autotune_batch(seqcdc_plan* plan, const seqcdc_file* h_fil
   u64 best_seg = 0;
   u32 best_span = 16, best_waves = 12;
   int best_mode = 0;
-  auto trial = [&](u64 seg, u32 span, u32 waves, int mode) -> int {
+  std::vector<Candidate> tried;
+  auto time_setting = [&](u64 seg, u32 span, u32 waves, int mode, int reps, double* ms) -> int {
     pl->seg_override = seg;
     pl->span_override = span;
     pl->waves_override = waves;
     pl->mode = mode;
+    return time_batch(pl, h_files, nfiles, h_params, nparams, d_cuts, h_cut_offsets, d_counts, st, e0, e1, reps, ms);
+  };
+  auto trial = [&](u64 seg, u32 span, u32 waves, int mode) -> int {
     double ms = 0;
-    int r = time_batch(pl, h_files, nfiles, h_params, nparams, d_cuts, h_cut_offsets, d_counts, st, e0, e1, 3, &ms);
+    int r = time_setting(seg, span, waves, mode, kTrialReps, &ms);
     if (r) return r;
+    tried.push_back(Candidate{seg, span, waves, mode, ms});
     if (ms < best) {
       best = ms;
       best_seg = seg;
@@ -200,6 +244,20 @@ extern "C" int seqcdc_autotune_batch(seqcdc_plan* plan, const seqcdc_file* h_fil
       if ((rc = trial(best_seg, s, w, 0))) break;
   }
   if (!rc) rc = trial(best_seg, best_span, 12, 1);
+  if (!rc) {  // the fastest candidates again, each timed over more calls
+    best = 1e30;
+    for (const Candidate& c : finalists(tried)) {
+      double ms = 0;
+      if ((rc = time_setting(c.seg, c.span, c.waves, c.mode, kFinalReps, &ms))) break;
+      if (ms < best) {
+        best = ms;
+        best_seg = c.seg;
+        best_span = c.span;
+        best_waves = c.waves;
+        best_mode = c.mode;
+      }
+    }
+  }
   if (!rc) {  // the plan keeps the fastest settings
     pl->seg_override = best_seg;
     pl->span_override = best_span;
